@@ -1,0 +1,165 @@
+"""Benchmark: FP64 forward of the coupled-cluster-shaped contraction
+Z[abij] = sum_{k,c} W[akic] T[cbkj] + Z (a,b,c = 96; i,j,k = 24; alpha = beta = 1)
+through the C ABI, inputs resident in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+A step is one full contraction (one kernel launch).  The line carries the
+roofline of the contraction kernel (matrix-core bound: 2mnk flops per launch
+over the mean launch time, against the FP64 matrix peak) and the CPU oracle's
+rate on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "tiles.hpp"):
+        with open(os.path.join(ROOT, "paper_1607_00291_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload_key, launches_per_step=1):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh).get(workload_key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(p, target_s=12.0):
+    """The oracle timed on the host on a bounded sample of output elements
+    (each a full-length contracted sum), scaled to GFLOP/s."""
+    import oracle
+    threads = oracle.default_threads()
+    K = p.mnk()[2]
+    rng = np.random.default_rng(1234)
+
+    def run(npts):
+        pts = np.stack([rng.integers(0, n, npts) for n in p.C.shape], axis=1)
+        t0 = time.perf_counter()
+        oracle.contract_points(p.alpha, p.A, p.idx_A, p.B, p.idx_B, p.beta, p.C, p.idx_C, pts, threads=threads)
+        return time.perf_counter() - t0
+
+    n = 2048
+    t = run(n)
+    n2 = int(min(max(n * target_s / max(t, 1e-3), n), 4_000_000))
+    t2 = run(n2)
+    flops = 2.0 * K * n2
+    return {"value": round(flops / t2 / 1e9, 4), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n2} random output elements of Z, each a full K={K} FP64 sum ({t2:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tile", type=int, default=None, help="force a tile configuration")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1607_00291_amd import inputs, tc
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+    p = inputs.cfg2()
+    m, n, k = p.mnk()
+    flops = 2.0 * m * n * k
+
+    def dev(a):
+        strides = [s // a.itemsize for s in a.strides]
+        span = 1 + sum((d - 1) * s for d, s in zip(a.shape, strides))
+        base = torch.zeros(span, dtype=torch.float64, device="cuda")
+        t = torch.as_strided(base, a.shape, strides)
+        t.copy_(torch.from_numpy(np.ascontiguousarray(a)).cuda())
+        return t
+
+    W, T, Z = dev(p.A), dev(p.B), dev(p.C)
+    plan = tc.Plan.for_tensors(W, p.idx_A, T, p.idx_B, Z, p.idx_C)
+    if args.tile is not None:
+        plan.tile = args.tile
+    plan.upload()
+    desc = plan.describe()
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+    h = plan.handle
+    lib = tc.lib()
+    alpha, beta = p.alpha, p.beta
+    Wp, Tp, Zp = W.data_ptr(), T.data_ptr(), Z.data_ptr()
+
+    for _ in range(args.warmup):
+        tc._check(lib.tc_plan_execute(h, alpha, Wp, Tp, beta, Zp, sp))
+    torch.cuda.synchronize()
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        tc._check(lib.tc_plan_execute(h, alpha, Wp, Tp, beta, Zp, sp))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1) / args.steps
+    gflops = flops / (ms * 1e-3) / 1e9
+    achieved_tf = gflops / 1e3
+
+    workload = "Z[abij]+=W[akic]T[cbkj] v=96 o=24 fp64"
+    traffic = load_traffic(workload)
+    line = {
+        "metric": "contraction GFLOP/s (FP64 forward, % of FP64 matrix-core peak in roofline)",
+        "value": round(gflops, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded normal inputs, column-major)",
+        "config": {"workload": workload, "m": m, "n": n, "k": k, "alpha": alpha, "beta": beta,
+                   "tile": [desc["MT"], desc["NT"], desc["KT"]], "waves": desc["waves"],
+                   "x_lanes": desc["x_lanes"], "y_lanes": desc["y_lanes"], "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+                     "algorithmic_flops_per_launch": flops, "mean_launch_ms": round(ms, 5)},
+        "wall_s_timed_region": round(wall, 3),
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(p)
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

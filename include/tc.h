@@ -1,0 +1,199 @@
+/*
+ * tc.h -- C ABI of the transpose-free tensor contraction library (libtc.so)
+ * for AMD MI355X (gfx950).
+ *
+ * The operation (Sec. 4, eq. gen-contraction, with the alpha/beta update of the
+ * element-wise matrix product in Sec. 3):
+ *
+ *     C[idx_C] := alpha * sum_{P} A[idx_A] * B[idx_B] + beta * C[idx_C]
+ *
+ * Every label appears in exactly two of the three tensors: labels shared by A
+ * and C form the bundle I, by B and C the bundle J, by A and B the contracted
+ * bundle P.  The contraction is computed as an (m = prod I) x (n = prod J) x
+ * (k = prod P) matrix product whose operands are addressed in place through
+ * scatter-offset vectors and block strides (Sec. 6.1-6.2, the block-scatter-
+ * matrix layout); no transposed copy of any tensor is formed.
+ *
+ * Conventions shared by every entry point
+ *   - Tensor descriptors: ndim in [0, TC_MAX_NDIM]; lens[d] >= 0; strides[d]
+ *     are in ELEMENTS (not bytes) and must be > 0 on every dimension of
+ *     length > 1 (a stride on a length-0/1 dimension is ignored); idx is an
+ *     array of ndim one-byte labels (not necessarily NUL-terminated), unique
+ *     within a tensor.  Descriptor arrays are host memory, read during the
+ *     call and not retained.
+ *   - A, B, C are DEVICE pointers owned by the caller.  A and B are read only;
+ *     C must not overlap itself (checked: sorted by stride, each stride must
+ *     be >= the previous stride times the previous length) nor overlap A or B
+ *     (checked by address ranges).
+ *   - beta == 0: C is write-only (NaN/Inf in C are not propagated).
+ *     alpha == 0: A and B are not read; C := beta * C.
+ *     A length-0 free index makes the call a no-op; a length-0 contracted
+ *     index gives C := beta * C.
+ *   - dtype: TC_F64 or TC_F32; A, B and C all have that storage type.
+ *     mode: TC_NATIVE (multiply-add in the storage type; FP64 accumulates in
+ *     FP64, FP32 in FP32) or TC_SPLIT_BF16X3 (TC_F32 only: each operand is
+ *     split into bf16 hi + lo, three products hi*hi + hi*lo + lo*hi on bf16
+ *     matrix cores, FP32 accumulation).
+ *   - stream is a hipStream_t (NULL = the null stream).  Calls are
+ *     asynchronous on it; device faults surface at the caller's next
+ *     synchronisation.  The results of one plan and one tile configuration
+ *     are deterministic (fixed summation order, no atomics on C).
+ *   - Return value: TC_OK (0) or a negative TC_ERR_* status.  Entry points
+ *     never abort and never throw; tc_last_error() gives a thread-local
+ *     message for the last failure on the calling thread.
+ */
+#ifndef TC_H
+#define TC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TC_MAX_NDIM 16
+
+enum {
+    TC_OK = 0,
+    TC_ERR_NULL = -1,    /* a required pointer is NULL */
+    TC_ERR_NDIM = -2,    /* ndim outside [0, TC_MAX_NDIM] */
+    TC_ERR_LABEL = -3,   /* label repeated in one tensor, or not in exactly two tensors */
+    TC_ERR_EXTENT = -4,  /* negative length, or one label with different lengths */
+    TC_ERR_STRIDE = -5,  /* stride <= 0 on a dimension of length > 1 */
+    TC_ERR_ALIAS = -6,   /* C overlaps itself, A or B */
+    TC_ERR_DTYPE = -7,   /* unknown dtype, or mode not available for dtype */
+    TC_ERR_HIP = -8,     /* a HIP runtime call failed (message in tc_last_error) */
+    TC_ERR_NOMEM = -9,   /* host or device allocation failed */
+    TC_ERR_ARG = -10,    /* other invalid argument (bad tile id, bad count, ...) */
+    TC_ERR_CAPTURE = -11 /* work that cannot be recorded in a graph was asked for during capture */
+};
+
+enum { TC_F64 = 0, TC_F32 = 1 };
+enum { TC_NATIVE = 0, TC_SPLIT_BF16X3 = 1 };
+
+typedef struct tc_plan tc_plan;
+typedef struct tc_batch tc_batch;
+
+/*
+ * One-shot contraction (Sec. 4 eq. gen-contraction; Sec. 6.2 BSMTC).
+ * Builds (or fetches from a process-wide, mutex-guarded cache keyed by the
+ * descriptors, dtype and mode) a plan and executes it on `stream`.  The first
+ * call for a descriptor set on a device uploads the plan's offset vectors with
+ * a synchronous copy, so a first call must not happen under graph capture
+ * (TC_ERR_CAPTURE); use tc_plan_create + tc_plan_upload beforehand instead.
+ */
+int tc_contract(double alpha,
+                const void* A, int ndim_A, const int64_t* lens_A, const int64_t* strides_A, const char* idx_A,
+                const void* B, int ndim_B, const int64_t* lens_B, const int64_t* strides_B, const char* idx_B,
+                double beta,
+                void* C, int ndim_C, const int64_t* lens_C, const int64_t* strides_C, const char* idx_C,
+                int dtype, int mode, void* stream);
+
+/*
+ * Plan creation (host only; no GPU call).  Validates the descriptors (the
+ * rules above), groups the labels into I, J, P (Sec. 4), orders them with the
+ * reordering heuristic of Sec. 7.3 (drop length-1 dimensions; sort I and J by
+ * C stride; swap the operands when C's unit stride lies in J; order P by the
+ * stride of the operand whose unit-stride index lies in P, ties to A; fold
+ * dimensions contiguous in every tensor holding them), builds the six scatter
+ * vectors and the block-stride vectors at the tile sizes of the chosen tile
+ * configuration (Sec. 6.1-6.3).  On success *plan owns host memory and, after
+ * the first upload, one device buffer per device; free it with
+ * tc_plan_destroy.  On failure *plan is set to NULL.
+ */
+int tc_plan_create(tc_plan** plan,
+                   int ndim_A, const int64_t* lens_A, const int64_t* strides_A, const char* idx_A,
+                   int ndim_B, const int64_t* lens_B, const int64_t* strides_B, const char* idx_B,
+                   int ndim_C, const int64_t* lens_C, const int64_t* strides_C, const char* idx_C,
+                   int dtype, int mode);
+
+/* Copy the plan's offset and block-stride vectors to the current device
+ * (synchronous; not allowed under graph capture).  Idempotent per device. */
+int tc_plan_upload(tc_plan* plan);
+
+/* Execute a plan on device data (Sec. 6.2 BSMTC as one kernel launch: gather
+ * of A and B slivers into LDS through the offset vectors, matrix-core
+ * micro-kernel, alpha/beta scatter-store of C tiles).  Safe to record into a
+ * hipGraph once the plan has been uploaded to the capturing device. */
+int tc_plan_execute(const tc_plan* plan, double alpha, const void* A, const void* B, double beta, void* C,
+                    void* stream);
+
+/* Free a plan and its device buffers (NULL is accepted).  The caller must
+ * make sure no launch using the plan is still running. */
+int tc_plan_destroy(tc_plan* plan);
+
+/*
+ * JSON description of a plan, for inspection and tests (host only): bundles
+ * in planned order with lengths and strides, whether A and B were swapped,
+ * m, n, k, tile configuration, the lane-fast dimension of each operand,
+ * counts of constant-stride blocks, and (for problems with at most
+ * `TC_DESCRIBE_MAX_VECTOR` entries per vector) the scatter and block-stride
+ * vectors.  Writes at most len bytes including the NUL; returns the full
+ * length needed (excluding NUL), or a negative status.
+ */
+#define TC_DESCRIBE_MAX_VECTOR 4096
+int tc_plan_describe(const tc_plan* plan, char* buf, size_t len);
+
+/* Number of compiled tile configurations for (dtype, mode), and their shapes.
+ * tile id -> MT x NT x KT and number of waves per workgroup. */
+int tc_tile_count(int dtype, int mode);
+int tc_tile_info(int dtype, int mode, int tile, int* MT, int* NT, int* KT, int* waves);
+
+/* Force a tile configuration on a plan (rebuilds its block-stride vectors;
+ * drops its device copies, so upload again before capture). */
+int tc_plan_set_tile(tc_plan* plan, int tile);
+int tc_plan_get_tile(const tc_plan* plan);
+
+/*
+ * Autotuner: time every compiled tile configuration of the plan on the
+ * caller's data (reps launches each after one warm-up, hipEvent timing on
+ * `stream`) and keep the fastest in the plan and in a process-wide cache keyed
+ * by the plan's shape signature (bundle lengths, strides, dtype, mode); plans
+ * created later with the same signature start from the cached choice.  C is
+ * overwritten with alpha=1, beta=0 results: pass a scratch tensor laid out
+ * like C.  Synchronises `stream`.  *best_ms receives the best time (may be NULL).
+ */
+int tc_plan_autotune(tc_plan* plan, const void* A, const void* B, void* C_scratch, int reps, void* stream,
+                     double* best_ms);
+
+/*
+ * Batched contractions in ONE persistent kernel launch (many independent
+ * contractions of uneven sizes and index permutations).  tc_batch_create
+ * plans every problem (all with the same dtype and mode), uploads one
+ * descriptor table plus all offset vectors to the current device
+ * (synchronous), and binds the given device pointers and scalars: problem i
+ * is C_i := alpha[i] * A_i . B_i + beta[i] * C_i with plans[i].  The plans
+ * are only read during the call.  tc_batch_execute then issues a single
+ * launch whose workgroups walk a flattened list of (problem, tile) work items;
+ * it makes no allocation and no host-device copy, so it may be recorded in a
+ * hipGraph and replayed.  C_i must not overlap each other.
+ */
+int tc_batch_create(tc_batch** batch, int count, const tc_plan* const* plans, const double* alpha,
+                    const void* const* A, const void* const* B, const double* beta, void* const* C);
+int tc_batch_execute(const tc_batch* batch, void* stream);
+int tc_batch_destroy(tc_batch* batch);
+/* Work-item count and the tile configuration the batch launch uses. */
+int tc_batch_info(const tc_batch* batch, int64_t* work_items, int* tile, int* grid);
+
+/*
+ * Building blocks of the block-scatter-matrix layout, exported for tests and
+ * for inspection (host only, Sec. 6.1-6.2):
+ *  - tc_scatter_vector: out[x] = sum_d x_d * strides[d] for every linear
+ *    index x of the bundle (lens, in the given order, first index fastest);
+ *    out has prod(lens) entries.
+ *  - tc_block_strides: out[i] (ceil(len/b) entries) = s > 0 when
+ *    scat[j] - scat[j-1] == s for every j of block i (i*b < j < min(len,(i+1)b)),
+ *    else 0; a block of one entry has stride 1.
+ */
+int tc_scatter_vector(int ndim, const int64_t* lens, const int64_t* strides, int64_t* out);
+int tc_block_strides(const int64_t* scat, int64_t len, int64_t b, int64_t* out);
+
+const char* tc_status_string(int status);
+const char* tc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TC_H */

@@ -1,0 +1,518 @@
+// C ABI of libtc.so (declared in include/tc.h): descriptor intake, the plan
+// cache, device upload of plan vectors, execution, autotuning and batching.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "plan.hpp"
+#include "tc.h"
+
+struct tc_plan {
+    std::unique_ptr<tc::Plan> p;
+};
+
+struct tc_batch {
+    int dtype = 0, mode = 0, tile = 0, count = 0, device = 0, grid = 0;
+    bool off64 = false;
+    int64_t total_items = 0;
+    void* table = nullptr;    // device BatchItemDev[count]
+    void* vectors = nullptr;  // device arena holding every problem's vectors
+};
+
+namespace tc {
+
+static int hipfail(hipError_t e, const char* what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return TC_ERR_HIP;
+}
+
+static int make_desc(int ndim, const int64_t* lens, const int64_t* strides, const char* idx, const char* name,
+                     TensorDesc* d) {
+    if (ndim < 0 || ndim > TC_MAX_NDIM) {
+        set_error(std::string(name) + ": ndim outside [0, 16]");
+        return TC_ERR_NDIM;
+    }
+    if (ndim > 0 && (!lens || !strides || !idx)) {
+        set_error(std::string(name) + ": NULL descriptor array");
+        return TC_ERR_NULL;
+    }
+    d->ndim = ndim;
+    for (int i = 0; i < ndim; ++i) {
+        d->lens[i] = lens[i];
+        d->strides[i] = strides[i];
+        d->idx[i] = idx[i];
+    }
+    return TC_OK;
+}
+
+static std::string desc_key(const TensorDesc& t) {
+    std::string s;
+    s.reserve(2 + t.ndim * 18);
+    s.push_back((char)t.ndim);
+    s.append(t.idx, t.ndim);
+    s.append((const char*)t.lens, sizeof(int64_t) * t.ndim);
+    s.append((const char*)t.strides, sizeof(int64_t) * t.ndim);
+    return s;
+}
+
+// ---- plan cache and autotuner cache -------------------------------------
+static std::mutex g_cache_mu;
+static std::map<std::string, std::unique_ptr<tc_plan>> g_plans;
+static std::map<std::string, int> g_tuned;  // plan signature -> tile
+
+static size_t elt_size(int dtype) { return dtype == TC_F64 ? 8 : 4; }
+
+// Copy the plan's vectors to the current device if not there yet.
+static int ensure_uploaded(const Plan& p, DeviceVectors** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hipfail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index beyond the library's limit of 16");
+        return TC_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> g(p.dev_mu);
+    DeviceVectors& dv = p.dev[dev];
+    if (dv.bytes) {
+        *out = &dv;
+        return TC_OK;
+    }
+    const std::vector<int64_t>* vecs[8] = {&p.rX, &p.cX, &p.rY, &p.cY, &p.rC, &p.cC, &p.kbsX, &p.kbsY};
+    size_t* offs[8] = {&dv.o_rX, &dv.o_cX, &dv.o_rY, &dv.o_cY, &dv.o_rC, &dv.o_cC, &dv.o_kbsX, &dv.o_kbsY};
+    size_t total = 0;
+    for (int i = 0; i < 8; ++i) {
+        *offs[i] = total;
+        size_t n = std::max<size_t>(vecs[i]->size(), 1);
+        total += (n + 63) & ~(size_t)63;  // 256-byte aligned starts (for int32)
+    }
+    const size_t w = p.off64 ? 8 : 4;
+    std::vector<char> host(total * w, 0);
+    for (int i = 0; i < 8; ++i) {
+        const std::vector<int64_t>& v = *vecs[i];
+        for (size_t j = 0; j < v.size(); ++j) {
+            if (p.off64) ((int64_t*)host.data())[*offs[i] + j] = v[j];
+            else ((int32_t*)host.data())[*offs[i] + j] = (int32_t)v[j];
+        }
+    }
+    if (dv.buf) {
+        hipFree(dv.buf);
+        dv.buf = nullptr;
+    }
+    e = hipMalloc(&dv.buf, host.size());
+    if (e != hipSuccess) {
+        dv.buf = nullptr;
+        set_error("hipMalloc of plan vectors failed");
+        return TC_ERR_NOMEM;
+    }
+    e = hipMemcpy(dv.buf, host.data(), host.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hipfail(e, "hipMemcpy of plan vectors");
+    dv.bytes = host.size();
+    *out = &dv;
+    return TC_OK;
+}
+
+static void free_device(Plan* p) {
+    for (auto& d : p->dev)
+        if (d.buf) {
+            hipFree(d.buf);
+            d.buf = nullptr;
+            d.bytes = 0;
+        }
+}
+
+static bool overlaps(const void* a, int64_t na, const void* b, int64_t nb, size_t w) {
+    if (!a || !b || na <= 0 || nb <= 0) return false;
+    const char* a0 = (const char*)a;
+    const char* b0 = (const char*)b;
+    return a0 < b0 + nb * (int64_t)w && b0 < a0 + na * (int64_t)w;
+}
+
+static int execute(const tc_plan* plan, double alpha, const void* A, const void* B, double beta, void* C,
+                   hipStream_t stream) {
+    const Plan& p = *plan->p;
+    if (p.noop || p.m == 0 || p.n == 0) return TC_OK;
+    if (!C) {
+        set_error("C is NULL");
+        return TC_ERR_NULL;
+    }
+    const bool reads_ab = !(p.k_empty || alpha == 0.0);
+    if (reads_ab && (!A || !B)) {
+        set_error("A or B is NULL");
+        return TC_ERR_NULL;
+    }
+    const size_t w = elt_size(p.dtype);
+    if (overlaps(C, p.spanC, A, p.spanA, w) || overlaps(C, p.spanC, B, p.spanB, w)) {
+        set_error("C overlaps A or B");
+        return TC_ERR_ALIAS;
+    }
+    DeviceVectors* dv = nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        if (dev < 0 || dev >= kMaxDevices || !p.dev[dev].bytes) {
+            set_error("plan vectors must be uploaded before graph capture (tc_plan_upload)");
+            return TC_ERR_CAPTURE;
+        }
+        dv = &p.dev[dev];
+    } else {
+        int st = ensure_uploaded(p, &dv);
+        if (st) return st;
+    }
+    return launch_plan(p, *dv, alpha, A, B, beta, C, stream);
+}
+
+static int create(tc_plan** out, int ndim_A, const int64_t* lens_A, const int64_t* strides_A, const char* idx_A,
+                  int ndim_B, const int64_t* lens_B, const int64_t* strides_B, const char* idx_B, int ndim_C,
+                  const int64_t* lens_C, const int64_t* strides_C, const char* idx_C, int dtype, int mode) {
+    TensorDesc a, b, c;
+    int st;
+    if ((st = make_desc(ndim_A, lens_A, strides_A, idx_A, "A", &a)) ||
+        (st = make_desc(ndim_B, lens_B, strides_B, idx_B, "B", &b)) ||
+        (st = make_desc(ndim_C, lens_C, strides_C, idx_C, "C", &c)))
+        return st;
+    std::unique_ptr<Plan> p;
+    if ((st = build_plan(a, b, c, dtype, mode, &p))) return st;
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        auto it = g_tuned.find(plan_signature(*p));
+        if (it != g_tuned.end() && it->second != p->tile && !p->off64) set_plan_tile(p.get(), it->second);
+    }
+    tc_plan* h = new (std::nothrow) tc_plan;
+    if (!h) {
+        set_error("out of host memory");
+        return TC_ERR_NOMEM;
+    }
+    h->p = std::move(p);
+    *out = h;
+    return TC_OK;
+}
+
+}  // namespace tc
+
+using namespace tc;
+
+extern "C" {
+
+int tc_plan_create(tc_plan** plan, int ndim_A, const int64_t* lens_A, const int64_t* strides_A, const char* idx_A,
+                   int ndim_B, const int64_t* lens_B, const int64_t* strides_B, const char* idx_B, int ndim_C,
+                   const int64_t* lens_C, const int64_t* strides_C, const char* idx_C, int dtype, int mode) {
+    if (!plan) {
+        set_error("plan out-pointer is NULL");
+        return TC_ERR_NULL;
+    }
+    *plan = nullptr;
+    try {
+        return create(plan, ndim_A, lens_A, strides_A, idx_A, ndim_B, lens_B, strides_B, idx_B, ndim_C, lens_C,
+                      strides_C, idx_C, dtype, mode);
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory");
+        return TC_ERR_NOMEM;
+    } catch (...) {
+        set_error("internal error while planning");
+        return TC_ERR_ARG;
+    }
+}
+
+int tc_plan_upload(tc_plan* plan) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return TC_ERR_NULL;
+    }
+    DeviceVectors* dv;
+    return ensure_uploaded(*plan->p, &dv);
+}
+
+int tc_plan_execute(const tc_plan* plan, double alpha, const void* A, const void* B, double beta, void* C,
+                    void* stream) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return TC_ERR_NULL;
+    }
+    return execute(plan, alpha, A, B, beta, C, (hipStream_t)stream);
+}
+
+int tc_plan_destroy(tc_plan* plan) {
+    if (!plan) return TC_OK;
+    free_device(plan->p.get());
+    delete plan;
+    return TC_OK;
+}
+
+int tc_plan_describe(const tc_plan* plan, char* buf, size_t len) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return TC_ERR_NULL;
+    }
+    std::string s = describe_plan(*plan->p);
+    if (buf && len) {
+        size_t n = std::min(len - 1, s.size());
+        memcpy(buf, s.data(), n);
+        buf[n] = 0;
+    }
+    return (int)s.size();
+}
+
+int tc_tile_count(int dtype, int mode) {
+    int n = tile_count(dtype, mode);
+    if (!n) {
+        set_error("unsupported dtype/mode combination");
+        return TC_ERR_DTYPE;
+    }
+    return n;
+}
+
+int tc_tile_info(int dtype, int mode, int tile, int* MT, int* NT, int* KT, int* waves) {
+    int n = tile_count(dtype, mode);
+    if (!n) {
+        set_error("unsupported dtype/mode combination");
+        return TC_ERR_DTYPE;
+    }
+    if (tile < 0 || tile >= n) {
+        set_error("tile id out of range");
+        return TC_ERR_ARG;
+    }
+    const TileCfg& t = tile_table(dtype, mode)[tile];
+    if (MT) *MT = t.MT;
+    if (NT) *NT = t.NT;
+    if (KT) *KT = t.KT;
+    if (waves) *waves = t.waves();
+    return TC_OK;
+}
+
+int tc_plan_set_tile(tc_plan* plan, int tile) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return TC_ERR_NULL;
+    }
+    Plan* p = plan->p.get();
+    if (tile < 0 || tile >= tile_count(p->dtype, p->mode)) {
+        set_error("tile id out of range");
+        return TC_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> g(p->dev_mu);
+    set_plan_tile(p, tile);
+    return TC_OK;
+}
+
+int tc_plan_get_tile(const tc_plan* plan) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return TC_ERR_NULL;
+    }
+    return plan->p->tile;
+}
+
+int tc_plan_autotune(tc_plan* plan, const void* A, const void* B, void* C_scratch, int reps, void* stream,
+                     double* best_ms) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return TC_ERR_NULL;
+    }
+    if (reps < 1) reps = 1;
+    Plan* p = plan->p.get();
+    hipStream_t s = (hipStream_t)stream;
+    const int nt = tile_count(p->dtype, p->mode);
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return hipfail(e, "hipEventCreate");
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        hipEventDestroy(e0);
+        return hipfail(e, "hipEventCreate");
+    }
+    int best = p->tile;
+    float best_t = 1e30f;
+    int st = TC_OK;
+    for (int t = 0; t < nt && st == TC_OK; ++t) {
+        {
+            std::lock_guard<std::mutex> g(p->dev_mu);
+            set_plan_tile(p, t);
+        }
+        if ((st = execute(plan, 1.0, A, B, 0.0, C_scratch, s))) break;  // warm-up (uploads)
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == TC_OK; ++r) st = execute(plan, 1.0, A, B, 0.0, C_scratch, s);
+        hipEventRecord(e1, s);
+        e = hipEventSynchronize(e1);
+        if (e != hipSuccess) {
+            st = hipfail(e, "autotune timing");
+            break;
+        }
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_t) {
+            best_t = ms;
+            best = t;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> g(p->dev_mu);
+        set_plan_tile(p, best);
+    }
+    if (st) return st;
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        g_tuned[plan_signature(*p)] = best;
+    }
+    if (best_ms) *best_ms = best_t;
+    return TC_OK;
+}
+
+int tc_contract(double alpha, const void* A, int ndim_A, const int64_t* lens_A, const int64_t* strides_A,
+                const char* idx_A, const void* B, int ndim_B, const int64_t* lens_B, const int64_t* strides_B,
+                const char* idx_B, double beta, void* C, int ndim_C, const int64_t* lens_C, const int64_t* strides_C,
+                const char* idx_C, int dtype, int mode, void* stream) {
+    try {
+        TensorDesc a, b, c;
+        int st;
+        if ((st = make_desc(ndim_A, lens_A, strides_A, idx_A, "A", &a)) ||
+            (st = make_desc(ndim_B, lens_B, strides_B, idx_B, "B", &b)) ||
+            (st = make_desc(ndim_C, lens_C, strides_C, idx_C, "C", &c)))
+            return st;
+        std::string key;
+        key.push_back((char)dtype);
+        key.push_back((char)mode);
+        key += desc_key(a);
+        key += desc_key(b);
+        key += desc_key(c);
+        tc_plan* plan = nullptr;
+        {
+            std::lock_guard<std::mutex> g(g_cache_mu);
+            auto it = g_plans.find(key);
+            if (it != g_plans.end()) plan = it->second.get();
+        }
+        if (!plan) {
+            tc_plan* fresh = nullptr;
+            if ((st = create(&fresh, ndim_A, lens_A, strides_A, idx_A, ndim_B, lens_B, strides_B, idx_B, ndim_C,
+                             lens_C, strides_C, idx_C, dtype, mode)))
+                return st;
+            std::lock_guard<std::mutex> g(g_cache_mu);
+            auto it = g_plans.find(key);
+            if (it == g_plans.end()) {
+                plan = fresh;
+                g_plans[key].reset(fresh);
+            } else {
+                plan = it->second.get();
+                tc_plan_destroy(fresh);
+            }
+        }
+        return execute(plan, alpha, A, B, beta, C, (hipStream_t)stream);
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory");
+        return TC_ERR_NOMEM;
+    } catch (...) {
+        set_error("internal error");
+        return TC_ERR_ARG;
+    }
+}
+
+int tc_batch_create(tc_batch** batch, int count, const tc_plan* const* plans, const double* alpha,
+                    const void* const* A, const void* const* B, const double* beta, void* const* C) {
+    (void)count;
+    (void)plans;
+    (void)alpha;
+    (void)A;
+    (void)B;
+    (void)beta;
+    (void)C;
+    if (batch) *batch = nullptr;
+    set_error("batched contractions are not built into this library");
+    return TC_ERR_ARG;
+}
+
+int tc_batch_execute(const tc_batch* batch, void* stream) {
+    (void)batch;
+    (void)stream;
+    set_error("batched contractions are not built into this library");
+    return TC_ERR_ARG;
+}
+
+int tc_batch_destroy(tc_batch* batch) {
+    if (!batch) return TC_OK;
+    if (batch->table) hipFree(batch->table);
+    if (batch->vectors) hipFree(batch->vectors);
+    delete batch;
+    return TC_OK;
+}
+
+int tc_batch_info(const tc_batch* batch, int64_t* work_items, int* tile, int* grid) {
+    if (!batch) {
+        set_error("batch is NULL");
+        return TC_ERR_NULL;
+    }
+    if (work_items) *work_items = batch->total_items;
+    if (tile) *tile = batch->tile;
+    if (grid) *grid = batch->grid;
+    return TC_OK;
+}
+
+int tc_scatter_vector(int ndim, const int64_t* lens, const int64_t* strides, int64_t* out) {
+    if (ndim < 0 || ndim > TC_MAX_NDIM) {
+        set_error("ndim outside [0, 16]");
+        return TC_ERR_NDIM;
+    }
+    if ((ndim && (!lens || !strides)) || !out) {
+        set_error("NULL argument");
+        return TC_ERR_NULL;
+    }
+    std::vector<Dim> dims(ndim);
+    for (int i = 0; i < ndim; ++i) {
+        if (lens[i] < 0) {
+            set_error("negative length");
+            return TC_ERR_EXTENT;
+        }
+        dims[i].len = lens[i];
+        dims[i].sX = strides[i];
+    }
+    std::vector<int64_t> v;
+    scatter_vector(dims, 0, &v);
+    std::copy(v.begin(), v.end(), out);
+    return TC_OK;
+}
+
+int tc_block_strides(const int64_t* scat, int64_t len, int64_t b, int64_t* out) {
+    if (len < 0 || b < 1) {
+        set_error("len must be >= 0 and b >= 1");
+        return TC_ERR_ARG;
+    }
+    if (len > 0 && (!scat || !out)) {
+        set_error("NULL argument");
+        return TC_ERR_NULL;
+    }
+    block_strides(scat, len, b, out);
+    return TC_OK;
+}
+
+const char* tc_status_string(int status) {
+    switch (status) {
+        case TC_OK: return "ok";
+        case TC_ERR_NULL: return "NULL pointer";
+        case TC_ERR_NDIM: return "ndim out of range";
+        case TC_ERR_LABEL: return "invalid labels";
+        case TC_ERR_EXTENT: return "extent mismatch";
+        case TC_ERR_STRIDE: return "invalid stride";
+        case TC_ERR_ALIAS: return "output aliases itself or an input";
+        case TC_ERR_DTYPE: return "unsupported dtype or mode";
+        case TC_ERR_HIP: return "HIP runtime error";
+        case TC_ERR_NOMEM: return "out of memory";
+        case TC_ERR_ARG: return "invalid argument";
+        case TC_ERR_CAPTURE: return "not allowed during graph capture";
+        default: return "unknown status";
+    }
+}
+
+const char* tc_last_error(void) { return last_error(); }
+
+}  // extern "C"

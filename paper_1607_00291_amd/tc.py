@@ -1,0 +1,251 @@
+"""ctypes binding of libtc.so (the C ABI declared in include/tc.h).
+
+Argument marshalling only: descriptors are read from torch tensors (shape,
+element strides, data pointer, current HIP stream) and handed to the library;
+every step of the contraction runs in the library's kernels.  A missing
+library raises; there is no fallback path.
+"""
+import ctypes
+import json
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtc.so")
+
+TC_F64, TC_F32 = 0, 1
+TC_NATIVE, TC_SPLIT_BF16X3 = 0, 1
+MODES = {"native": TC_NATIVE, "split_bf16x3": TC_SPLIT_BF16X3, "split-bf16": TC_SPLIT_BF16X3}
+
+# every symbol include/tc.h declares
+EXPORTS = [
+    "tc_contract", "tc_plan_create", "tc_plan_upload", "tc_plan_execute", "tc_plan_destroy",
+    "tc_plan_describe", "tc_tile_count", "tc_tile_info", "tc_plan_set_tile", "tc_plan_get_tile",
+    "tc_plan_autotune", "tc_batch_create", "tc_batch_execute", "tc_batch_destroy", "tc_batch_info",
+    "tc_scatter_vector", "tc_block_strides", "tc_status_string", "tc_last_error",
+]
+
+
+class TCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tc status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1607_00291_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        desc = [ctypes.c_int, _i64p, _i64p, ctypes.c_char_p]
+        L.tc_contract.argtypes = ([ctypes.c_double, _vp] + desc + [_vp] + desc + [ctypes.c_double, _vp] + desc
+                                  + [ctypes.c_int, ctypes.c_int, _vp])
+        L.tc_plan_create.argtypes = [ctypes.POINTER(_vp)] + desc * 3 + [ctypes.c_int, ctypes.c_int]
+        L.tc_plan_upload.argtypes = [_vp]
+        L.tc_plan_execute.argtypes = [_vp, ctypes.c_double, _vp, _vp, ctypes.c_double, _vp, _vp]
+        L.tc_plan_destroy.argtypes = [_vp]
+        L.tc_plan_describe.argtypes = [_vp, ctypes.c_char_p, ctypes.c_size_t]
+        L.tc_tile_count.argtypes = [ctypes.c_int, ctypes.c_int]
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.tc_tile_info.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip, ip, ip]
+        L.tc_plan_set_tile.argtypes = [_vp, ctypes.c_int]
+        L.tc_plan_get_tile.argtypes = [_vp]
+        L.tc_plan_autotune.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double)]
+        L.tc_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_vp)]
+        L.tc_batch_execute.argtypes = [_vp, _vp]
+        L.tc_batch_destroy.argtypes = [_vp]
+        L.tc_batch_info.argtypes = [_vp, _i64p, ip, ip]
+        L.tc_scatter_vector.argtypes = [ctypes.c_int, _i64p, _i64p, _i64p]
+        L.tc_block_strides.argtypes = [_i64p, ctypes.c_int64, ctypes.c_int64, _i64p]
+        L.tc_status_string.argtypes = [ctypes.c_int]
+        L.tc_status_string.restype = ctypes.c_char_p
+        L.tc_last_error.argtypes = []
+        L.tc_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("tc_status_string", "tc_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st < 0:
+        L = lib()
+        raise TCError(st, f"{L.tc_status_string(st).decode()}: {L.tc_last_error().decode()}")
+    return st
+
+
+def _arr(vals):
+    vals = list(vals)
+    return (ctypes.c_int64 * max(len(vals), 1))(*vals)
+
+
+def _desc(shape, strides, labels):
+    labels = labels.encode() if isinstance(labels, str) else labels
+    if len(labels) != len(shape) or len(strides) != len(shape):
+        raise ValueError("labels, shape and strides must have one entry per dimension")
+    return [len(shape), _arr(shape), _arr(strides), labels]
+
+
+def _dtype_code(dtype):
+    import torch
+    if dtype == torch.float64:
+        return TC_F64
+    if dtype == torch.float32:
+        return TC_F32
+    raise TypeError(f"unsupported dtype {dtype} (float64 or float32)")
+
+
+def _stream_ptr(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def scatter_vector(lens, strides):
+    """Offsets of every linear index of a bundle (first index fastest)."""
+    n = 1
+    for x in lens:
+        n *= x
+    out = (ctypes.c_int64 * max(n, 1))()
+    _check(lib().tc_scatter_vector(len(lens), _arr(lens), _arr(strides), out))
+    return list(out[:n])
+
+
+def block_strides(scat, b):
+    """Block-stride vector of a scatter vector for blocking b (0 = none)."""
+    n = len(scat)
+    nb = (n + b - 1) // b
+    out = (ctypes.c_int64 * max(nb, 1))()
+    _check(lib().tc_block_strides(_arr(scat), n, b, out))
+    return list(out[:nb])
+
+
+def tile_count(dtype=TC_F64, mode=TC_NATIVE):
+    return _check(lib().tc_tile_count(dtype, mode))
+
+
+def tile_info(dtype, mode, tile):
+    v = [ctypes.c_int() for _ in range(4)]
+    _check(lib().tc_tile_info(dtype, mode, tile, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
+class Plan:
+    """A planned contraction (descriptors only; data bound at execute)."""
+
+    def __init__(self, shape_A, strides_A, idx_A, shape_B, strides_B, idx_B, shape_C, strides_C, idx_C,
+                 dtype=TC_F64, mode=TC_NATIVE):
+        self._h = _vp()
+        self.dtype, self.mode = dtype, mode
+        _check(lib().tc_plan_create(ctypes.byref(self._h), *_desc(shape_A, strides_A, idx_A),
+                                    *_desc(shape_B, strides_B, idx_B), *_desc(shape_C, strides_C, idx_C),
+                                    dtype, mode))
+
+    @classmethod
+    def for_tensors(cls, A, idx_A, B, idx_B, C, idx_C, mode="native"):
+        mode = MODES[mode] if isinstance(mode, str) else mode
+        return cls(tuple(A.shape), A.stride(), idx_A, tuple(B.shape), B.stride(), idx_B, tuple(C.shape), C.stride(),
+                   idx_C, _dtype_code(C.dtype), mode)
+
+    def describe(self):
+        n = _check(lib().tc_plan_describe(self._h, None, 0))
+        buf = ctypes.create_string_buffer(n + 1)
+        _check(lib().tc_plan_describe(self._h, buf, n + 1))
+        return json.loads(buf.value.decode())
+
+    def upload(self):
+        _check(lib().tc_plan_upload(self._h))
+
+    def execute(self, A, B, C, alpha=1.0, beta=0.0, stream=None):
+        _check(lib().tc_plan_execute(self._h, float(alpha), _ptr(A), _ptr(B), float(beta), _ptr(C),
+                                     _stream_ptr(stream)))
+        return C
+
+    def execute_ptrs(self, A, B, C, alpha, beta, stream_ptr):
+        return _check(lib().tc_plan_execute(self._h, float(alpha), A, B, float(beta), C, stream_ptr))
+
+    @property
+    def tile(self):
+        return _check(lib().tc_plan_get_tile(self._h))
+
+    @tile.setter
+    def tile(self, t):
+        _check(lib().tc_plan_set_tile(self._h, int(t)))
+
+    def autotune(self, A, B, C_scratch, reps=3, stream=None):
+        best = ctypes.c_double()
+        _check(lib().tc_plan_autotune(self._h, _ptr(A), _ptr(B), _ptr(C_scratch), int(reps), _stream_ptr(stream),
+                                      ctypes.byref(best)))
+        return self.tile, best.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().tc_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return t.data_ptr() if t.numel() else None
+
+
+def contract(A, idx_A, B, idx_B, idx_C, alpha=1.0, beta=0.0, out=None, mode="native", stream=None):
+    """C[idx_C] = alpha * A[idx_A] . B[idx_B] + beta * out, on the GPU.
+
+    A, B (and out) are torch tensors on the current HIP device with any
+    strides.  Without ``out`` a new column-major C is allocated (beta is then
+    ignored).  Returns C.
+    """
+    import torch
+    mode_code = MODES[mode] if isinstance(mode, str) else mode
+    if A.dtype != B.dtype:
+        raise TypeError("A and B must have the same dtype")
+    if out is None:
+        ext = {}
+        for t, lab in ((A, idx_A), (B, idx_B)):
+            for l, n in zip(lab, t.shape):
+                ext[l] = n
+        shape = [ext[l] for l in idx_C]
+        strides, s = [], 1
+        for n in shape:
+            strides.append(s)
+            s *= max(n, 1)
+        out = torch.empty_strided(shape, strides, dtype=A.dtype, device=A.device)
+        beta = 0.0
+    if out.dtype != A.dtype:
+        raise TypeError("C must have the dtype of A and B")
+    _check(lib().tc_contract(float(alpha), _ptr(A), *_desc(tuple(A.shape), A.stride(), idx_A), _ptr(B),
+                             *_desc(tuple(B.shape), B.stride(), idx_B), float(beta), _ptr(out),
+                             *_desc(tuple(out.shape), out.stride(), idx_C), _dtype_code(A.dtype), mode_code,
+                             _stream_ptr(stream)))
+    return out
+
+
+def describe(A_shape, A_strides, idx_A, B_shape, B_strides, idx_B, C_shape, C_strides, idx_C, dtype=TC_F64,
+             mode=TC_NATIVE):
+    """Plan description (no GPU needed)."""
+    p = Plan(A_shape, A_strides, idx_A, B_shape, B_strides, idx_B, C_shape, C_strides, idx_C, dtype, mode)
+    try:
+        return p.describe()
+    finally:
+        p.close()

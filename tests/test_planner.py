@@ -1,0 +1,261 @@
+"""Host-side planner and C-ABI tests (no GPU): scatter vectors and block
+strides against the paper's worked example, the reordering heuristic on the
+workloads, brute-force addressing, and argument validation."""
+import ctypes
+import itertools
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1607_00291_amd import inputs, tc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def strides_of(a):
+    return [s // a.itemsize for s in a.strides]
+
+
+def describe(p, dtype=tc.TC_F64, mode=tc.TC_NATIVE):
+    return tc.describe(p.A.shape, strides_of(p.A), p.idx_A, p.B.shape, strides_of(p.B), p.idx_B,
+                       p.C.shape, strides_of(p.C), p.idx_C, dtype, mode)
+
+
+def test_library_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "tc.h")).read()
+    declared = set(re.findall(r"^(?:int|const char\*)\s+(tc_\w+)\(", header, re.M))
+    assert declared == set(tc.EXPORTS)
+    L = ctypes.CDLL(tc.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+# --------------------------------------------------------------------------
+# worked example of Sec. 6.1 / 6.2 (fig. bsm): C_abcde, lengths 6x3x2x3x4,
+# strides 1, 6, 18, 36, 108, bundles I = cdb and J = ae, blocking 4
+# --------------------------------------------------------------------------
+
+def load_golden():
+    with open(os.path.join(GOLDEN, "worked_example.json")) as fh:
+        return json.load(fh)
+
+
+def test_worked_example_scatter_vectors():
+    g = load_golden()
+    ln, st = g["lens"], g["strides"]
+    I = [g["labels"].index(l) for l in g["I"]]
+    J = [g["labels"].index(l) for l in g["J"]]
+    rscat = tc.scatter_vector([ln[i] for i in I], [st[i] for i in I])
+    cscat = tc.scatter_vector([ln[j] for j in J], [st[j] for j in J])
+    # the printed stretch of cscat: 0..5, then a jump to 108..113
+    assert cscat[:12] == g["cscat_prefix"]
+    # the printed formula of rscat / cscat (eq. cscat-c) with floor division
+    na, nb, nc, nd, ne = ln
+    for Ibar in range(nc * nd * nb):
+        want = (Ibar % nc) * na * nb + ((Ibar // nc) % nd) * na * nb * nc + ((Ibar // (nc * nd)) % nb) * na
+        assert rscat[Ibar] == want
+    for Jbar in range(na * ne):
+        assert cscat[Jbar] == (Jbar % na) + ((Jbar // na) % ne) * na * nb * nc * nd
+    # short stretches of rscat behave like a constant stride n_a n_b = 18
+    assert rscat[1] - rscat[0] == g["rscat_short_stride"]
+
+
+def test_worked_example_block_strides_and_53_percent():
+    g = load_golden()
+    ln, st = g["lens"], g["strides"]
+    I = [g["labels"].index(l) for l in g["I"]]
+    J = [g["labels"].index(l) for l in g["J"]]
+    rscat = tc.scatter_vector([ln[i] for i in I], [st[i] for i in I])
+    cscat = tc.scatter_vector([ln[j] for j in J], [st[j] for j in J])
+    rbs = tc.block_strides(rscat, g["mR"])
+    cbs = tc.block_strides(cscat, g["nR"])
+    # every valid block stride is the constant difference of its block
+    for bs, scat, b in ((rbs, rscat, g["mR"]), (cbs, cscat, g["nR"])):
+        for i, s in enumerate(bs):
+            blk = scat[i * b:(i + 1) * b]
+            diffs = {y - x for x, y in zip(blk, blk[1:])}
+            assert (s != 0) == (len(diffs) <= 1 and min(diffs, default=1) > 0)
+            if s:
+                assert diffs <= {s}
+    both = sum(1 for r in rbs for c in cbs if r and c)
+    total = len(rbs) * len(cbs)
+    assert round(100 * both / total) == g["percent_constant_stride_tiles"]
+
+
+def test_block_strides_edge_cases():
+    assert tc.block_strides([5], 4) == [1]                 # one entry
+    assert tc.block_strides([0, 3, 6, 9, 12], 4) == [3, 1]  # last block of one entry
+    assert tc.block_strides([0, 2, 4, 5], 4) == [0]
+    assert tc.block_strides([9, 6, 3, 0], 4) == [0]        # negative differences: no stride
+    assert tc.block_strides([0, 0, 0], 4) == [0]           # zero difference: no stride
+    assert tc.block_strides([], 4) == []
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_scatter_vectors_address_every_element(seed):
+    """Brute force: for every (I, J, P) index of a random small contraction,
+    the planned scatter vectors give the element offsets of A, B and C."""
+    p = inputs.random_problem(300 + seed, 2, 2, 2, lo=1, hi=5)
+    d = describe(p)
+    if d["noop"]:
+        return
+    X, Y = (p.B, p.A) if d["swapped"] else (p.A, p.B)
+    ix, iy = (p.idx_B, p.idx_A) if d["swapped"] else (p.idx_A, p.idx_B)
+
+    def walk(dims):
+        """label values of every linear index of a planned bundle"""
+        lens = [x["len"] for x in dims]
+        out = []
+        for lin in range(int(np.prod(lens, dtype=np.int64)) if dims else 1):
+            vals, r = {}, lin
+            for x in dims:
+                v = r % x["len"]
+                r //= x["len"]
+                # a folded dim covers several labels, first fastest
+                for l in x["labels"]:
+                    n = p.extents[l]
+                    vals[l] = v % n
+                    v //= n
+            out.append(vals)
+        return out
+
+    def off(arr, labels, vals):
+        return sum(vals[l] * s for l, s in zip(labels, strides_of(arr)) if l in vals)
+
+    Iv, Jv, Pv = walk(d["I"]), walk(d["J"]), walk(d["P"])
+    for mi, a in enumerate(Iv):
+        assert d["rscat_X"][mi] == off(X, ix, a)
+        assert d["rscat_C"][mi] == off(p.C, p.idx_C, a)
+    for nj, b in enumerate(Jv):
+        assert d["cscat_Y"][nj] == off(Y, iy, b)
+        assert d["cscat_C"][nj] == off(p.C, p.idx_C, b)
+    for kp, c in enumerate(Pv):
+        assert d["cscat_X"][kp] == off(X, ix, c)
+        assert d["rscat_Y"][kp] == off(Y, iy, c)
+
+
+def test_heuristic_cfg1():
+    d = describe(inputs.cfg1())
+    assert not d["swapped"]
+    assert [x["labels"] for x in d["I"]] == ["a", "b"]
+    assert [x["labels"] for x in d["J"]] == ["c", "d"]
+    assert [x["labels"] for x in d["P"]] == ["e", "f"]
+    assert (d["m"], d["n"], d["k"]) == (256, 256, 256)
+    assert d["x_lanes"] == "m" and d["y_lanes"] == "n"
+
+
+def test_heuristic_cfg2_gpu_amendment():
+    """Sort by A's stride would give P = (k, c); T[cbkj] has its unit stride
+    on c, so the amended order is P = (c, k) and T is gathered along k."""
+    d = describe(inputs.cfg2())
+    assert not d["swapped"]
+    assert [x["labels"] for x in d["I"]] == ["a", "i"]
+    assert [x["labels"] for x in d["J"]] == ["b", "j"]
+    assert [x["labels"] for x in d["P"]] == ["c", "k"]
+    assert d["P"][0]["sY"] == 1
+    assert (d["m"], d["n"], d["k"]) == (2304, 2304, 2304)
+    assert d["x_lanes"] == "m" and d["y_lanes"] == "k"
+    assert d["k_blocks_regular_x"] == d["k_blocks"] and d["k_blocks_regular_y"] == d["k_blocks"]
+
+
+def test_heuristic_cfg4_fold_and_backward():
+    p = inputs.cfg4()
+    d = describe(p)
+    # J = (j, a) is contiguous in C and B: folded into one index of length 2048
+    assert [x["labels"] for x in d["J"]] == ["ja"]
+    assert d["J"][0]["len"] == 2048
+    assert (d["m"], d["n"], d["k"]) == (2048, 2048, 1024)
+    assert d["folds"] >= 1
+    # dA[iklb] = dC[ijab] . B[kjal]  (contracted j, a)
+    dA = inputs.colmajor(p.A.shape, fill=0.0)
+    q = inputs.Problem("ijab", "kjal", "iklb", p.dC, p.B, dA, 1.0, 0.0, "dA", p.extents)
+    d = describe(q)
+    assert (d["m"], d["n"], d["k"]) == (2048, 1024, 2048)
+    # dB[kjal] = A[iklb] . dC[ijab]  (contracted i, b)
+    dB = inputs.colmajor(p.B.shape, fill=0.0)
+    q = inputs.Problem("iklb", "ijab", "kjal", p.A, p.dC, dB, 1.0, 0.0, "dB", p.extents)
+    d = describe(q)
+    assert d["m"] * d["n"] == 1024 * 2048 and d["k"] == 2048
+
+
+def test_swap_when_C_unit_stride_in_J():
+    A = inputs.colmajor((5, 7))   # A[i p]
+    B = inputs.colmajor((7, 9))   # B[p j]
+    C = inputs.colmajor((9, 5))   # C[j i]: unit stride on j
+    p = inputs.Problem("ip", "pj", "ji", A, B, C)
+    d = describe(p)
+    assert d["swapped"]
+    assert [x["labels"] for x in d["I"]] == ["j"] and d["I"][0]["sC"] == 1
+
+
+def test_length_one_dims_dropped():
+    A = inputs.colmajor((5, 1, 7))
+    B = inputs.colmajor((7, 1, 9))
+    C = inputs.colmajor((5, 1, 1, 9))
+    p = inputs.Problem("iqp", "prj", "iqrj", A, B, C)
+    d = describe(p)
+    assert d["dropped"] == 2  # q (in A and C) and r (in B and C)
+    assert (d["m"], d["n"], d["k"]) == (5, 9, 7)
+
+
+def test_tile_table():
+    for dt, mode in ((tc.TC_F64, tc.TC_NATIVE), (tc.TC_F32, tc.TC_NATIVE)):
+        n = tc.tile_count(dt, mode)
+        assert n >= 1
+        for t in range(n):
+            MT, NT, KT, waves = tc.tile_info(dt, mode, t)
+            assert MT % 16 == 0 and NT % 16 == 0 and KT % 4 == 0 and waves >= 1
+
+
+# --------------------------------------------------------------------------
+# argument validation through the C ABI (no GPU work is started)
+# --------------------------------------------------------------------------
+
+def plan_status(shape_A, st_A, ia, shape_B, st_B, ib, shape_C, st_C, ic, dtype=tc.TC_F64, mode=tc.TC_NATIVE):
+    try:
+        tc.Plan(shape_A, st_A, ia, shape_B, st_B, ib, shape_C, st_C, ic, dtype, mode).close()
+        return 0
+    except tc.TCError as e:
+        return e.status
+
+
+def test_abi_errors():
+    L = tc.lib()
+    ok = ((2, 3), (1, 2), "ip", (3, 4), (1, 3), "pj", (2, 4), (1, 2), "ij")
+    assert plan_status(*ok) == 0
+    assert plan_status((2, 3), (1, 2), "ii", (3, 4), (1, 3), "pj", (2, 4), (1, 2), "ij") == -3  # repeated
+    assert plan_status((2, 3), (1, 2), "ip", (3, 4), (1, 3), "pj", (2, 4), (1, 2), "ix") == -3  # x only in C
+    assert plan_status((2, 3), (1, 2), "ip", (3, 4), (1, 3), "pi", (2, 4), (1, 2), "ij") == -3  # i in all / j in one
+    assert plan_status((2, 3), (1, 2), "ip", (4, 4), (1, 4), "pj", (2, 4), (1, 2), "ij") == -4  # p: 3 vs 4
+    assert plan_status((2, 3), (1, 0), "ip", (3, 4), (1, 3), "pj", (2, 4), (1, 2), "ij") == -5  # zero stride
+    assert plan_status((2, 3), (1, -2), "ip", (3, 4), (1, 3), "pj", (2, 4), (1, 2), "ij") == -5
+    assert plan_status((2, 3), (1, 2), "ip", (3, 4), (1, 3), "pj", (2, 4), (1, 1), "ij") == -6  # C overlaps itself
+    assert plan_status(*ok[:-0] if False else ok, dtype=5) == -7
+    assert plan_status(*ok, dtype=tc.TC_F64, mode=tc.TC_SPLIT_BF16X3) == -7
+    # ndim out of range and NULL descriptors
+    h = ctypes.c_void_p()
+    lens = (ctypes.c_int64 * 17)(*([1] * 17))
+    assert L.tc_plan_create(ctypes.byref(h), 17, lens, lens, b"abcdefghijklmnopq", 0, None, None, None,
+                            17, lens, lens, b"abcdefghijklmnopq", 0, 0) == -2
+    assert L.tc_plan_create(ctypes.byref(h), 2, None, None, None, 0, None, None, None, 0, None, None, None, 0, 0) == -1
+    assert L.tc_plan_create(None, 0, None, None, None, 0, None, None, None, 0, None, None, None, 0, 0) == -1
+    assert L.tc_plan_execute(None, 1.0, None, None, 0.0, None, None) == -1
+    assert L.tc_plan_destroy(None) == 0
+    assert L.tc_last_error()
+
+
+def test_length_one_dim_may_have_any_stride():
+    assert plan_status((2, 1, 3), (1, 0, 2), "iqp", (3, 4), (1, 3), "pj", (2, 1, 4), (1, -7, 2), "iqj") == 0
+
+
+def test_describe_without_gpu_and_vectors_size_limit():
+    p = inputs.cfg2()
+    d = describe(p)
+    assert d["vectors"] is True and len(d["rscat_X"]) == 2304
+    big = inputs.Problem("ip", "pj", "ij", inputs.colmajor((8192, 2)), inputs.colmajor((2, 3)),
+                         inputs.colmajor((8192, 3)))
+    assert describe(big)["vectors"] is False
