@@ -76,18 +76,6 @@ struct KArgs {
     T alpha, beta;
 };
 
-template <int MT, int NT, int KT, int WM, int WN>
-struct Shape {
-    static constexpr int NTHR = WM * WN * 64;
-    static constexpr int WTM = MT / WM, WTN = NT / WN;  // outputs of one wave
-    static constexpr int FM = WTM / 16, FN = WTN / 16;  // 16x16 fragments per wave
-    static constexpr int EX = MT * KT / NTHR;           // X elements per thread per stage
-    static constexpr int EY = NT * KT / NTHR;
-    static_assert(KT % 4 == 0, "KT must be a multiple of the MFMA depth");
-    static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tiles are made of 16x16 fragments");
-    static_assert((MT * KT) % NTHR == 0 && (NT * KT) % NTHR == 0, "stage must split evenly over threads");
-};
-
 // LDS row pitch (in elements) of a k-major stage: one element of padding when
 // the lanes of the gather run along k (consecutive lanes then write to
 // consecutive LDS rows, and the pad spreads them over the banks).
@@ -96,175 +84,292 @@ struct Pitch {
     static constexpr int value = LANES_ALONG_ROW ? W : W + 1;
 };
 
-template <typename T, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
-struct Smem {
-    static constexpr int LDX = Pitch<MT, XM>::value;
-    static constexpr int LDY = Pitch<NT, YN>::value;
-    static constexpr int XS = KT * LDX, YS = KT * LDY;  // one stage
-    static constexpr int ELEMS = 2 * (XS + YS);
-};
+// The pack stage of one tile: MT x KT slivers of X and KT x NT slivers of Y
+// gathered through the offset vectors into registers, then written to a
+// k-major LDS stage.  Element e = tid + NTHR * i of a stage is (row, kk) with
+// the row index fastest when the operand's lanes run along m (XM) / n (YN),
+// and kk fastest otherwise.
+template <typename T, typename OffT, int MT, int NT, int KT, int NTHR, bool XM, bool YN>
+struct Pack {
+    static constexpr int EX = MT * KT / NTHR, EY = NT * KT / NTHR;
+    static constexpr int LDX = Pitch<MT, XM>::value, LDY = Pitch<NT, YN>::value;
+    static constexpr int XS = KT * LDX, YS = KT * LDY;  // elements of one stage
+    static constexpr int ELEMS = 2 * (XS + YS);          // double-buffered
+    static_assert((MT * KT) % NTHR == 0 && (NT * KT) % NTHR == 0, "stage must split evenly over threads");
 
-// One output tile of one problem.  `smem` holds two stages of X and Y.
-template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
-__device__ __forceinline__ void tile_body(const KArgs<T, OffT>& a, int64_t tile, T* smem) {
-    typedef Shape<MT, NT, KT, WM, WN> S;
-    typedef Smem<T, MT, NT, KT, WM, WN, XM, YN> L;
-    typedef Mfma<T> M;
-    typedef typename M::acc_t acc_t;
-    constexpr int NTHR = S::NTHR, EX = S::EX, EY = S::EY, FM = S::FM, FN = S::FN;
-    constexpr int LDX = L::LDX, LDY = L::LDY;
+    static __device__ __forceinline__ int xrow(int e) { return XM ? e % MT : e / KT; }
+    static __device__ __forceinline__ int xk(int e) { return XM ? e / MT : e % KT; }
+    static __device__ __forceinline__ int ycol(int e) { return YN ? e % NT : e / KT; }
+    static __device__ __forceinline__ int yk(int e) { return YN ? e / NT : e % KT; }
 
-    T* sX = smem;                // [2][KT][LDX]
-    T* sY = smem + 2 * L::XS;    // [2][KT][LDY]
+    OffT xo[EX], yo[EY];  // row offsets of X / column offsets of Y, fixed per tile
+    bool xv[EX], yv[EY];
+    T rx[EX], ry[EY];     // one stage in flight
 
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % WM, wn = wave / WM;
-
-    const int64_t tm = tile % a.tiles_m, tn = tile / a.tiles_m;
-    const OffT m0 = (OffT)(tm * MT), n0 = (OffT)(tn * NT);
-
-    // per-thread gather coordinates; element e = tid + NTHR * i of a stage is
-    // (row r, k kk) of X with r fastest when XM, kk fastest otherwise
-    OffT xo[EX];
-    bool xv[EX];
+    __device__ __forceinline__ void init(const KArgs<T, OffT>& a, OffT m0, OffT n0, int tid) {
 #pragma unroll
-    for (int i = 0; i < EX; ++i) {
-        const int e = tid + NTHR * i;
-        const int r = XM ? e % MT : e / KT;
-        const OffT mm = m0 + r;
-        xv[i] = mm < a.m;
-        xo[i] = xv[i] ? a.rX[mm] : OffT(0);
-    }
-    OffT yo[EY];
-    bool yv[EY];
+        for (int i = 0; i < EX; ++i) {
+            const OffT mm = m0 + xrow(tid + NTHR * i);
+            xv[i] = mm < a.m;
+            xo[i] = xv[i] ? a.rX[mm] : OffT(0);
+        }
 #pragma unroll
-    for (int i = 0; i < EY; ++i) {
-        const int e = tid + NTHR * i;
-        const int c = YN ? e % NT : e / KT;
-        const OffT nn = n0 + c;
-        yv[i] = nn < a.n;
-        yo[i] = yv[i] ? a.cY[nn] : OffT(0);
+        for (int i = 0; i < EY; ++i) {
+            const OffT nn = n0 + ycol(tid + NTHR * i);
+            yv[i] = nn < a.n;
+            yo[i] = yv[i] ? a.cY[nn] : OffT(0);
+        }
     }
 
-    acc_t acc[FM][FN];
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[i][j][r] = T(0);
-
-    T rx[EX], ry[EY];
-    const OffT nkb = (a.k + KT - 1) / KT;
-
-    auto gload = [&](OffT kb) {
+    // Global gather of k block kb.  A valid block stride (Sec. 6.2) replaces
+    // the per-element scatter-vector reads along k.
+    __device__ __forceinline__ void load(const KArgs<T, OffT>& a, OffT kb, int tid) {
         const OffT k0 = kb * KT;
         const OffT sx = a.kbsX[kb], sy = a.kbsY[kb];
         const OffT bx = a.cX[k0], by = a.rY[k0];
 #pragma unroll
         for (int i = 0; i < EX; ++i) {
-            const int e = tid + NTHR * i;
-            const int kk = XM ? e / MT : e % KT;
+            const int kk = xk(tid + NTHR * i);
             const OffT kg = k0 + kk;
             T v = T(0);
-            if (xv[i] && kg < a.k) {
-                const OffT ko = sx ? bx + (OffT)kk * sx : a.cX[kg];
-                v = a.X[xo[i] + ko];
-            }
+            if (xv[i] && kg < a.k) v = a.X[xo[i] + (sx ? bx + (OffT)kk * sx : a.cX[kg])];
             rx[i] = v;
         }
 #pragma unroll
         for (int i = 0; i < EY; ++i) {
-            const int e = tid + NTHR * i;
-            const int kk = YN ? e / NT : e % KT;
+            const int kk = yk(tid + NTHR * i);
             const OffT kg = k0 + kk;
             T v = T(0);
-            if (yv[i] && kg < a.k) {
-                const OffT ko = sy ? by + (OffT)kk * sy : a.rY[kg];
-                v = a.Y[yo[i] + ko];
-            }
+            if (yv[i] && kg < a.k) v = a.Y[yo[i] + (sy ? by + (OffT)kk * sy : a.rY[kg])];
             ry[i] = v;
         }
-    };
-    auto lstore = [&](int buf) {
-        T* bx = sX + buf * L::XS;
-        T* by = sY + buf * L::YS;
+    }
+
+    __device__ __forceinline__ void store(T* smem, int buf, int tid) const {
+        T* bx = smem + buf * XS;
+        T* by = smem + 2 * XS + buf * YS;
 #pragma unroll
         for (int i = 0; i < EX; ++i) {
             const int e = tid + NTHR * i;
-            const int r = XM ? e % MT : e / KT;
-            const int kk = XM ? e / MT : e % KT;
-            bx[kk * LDX + r] = rx[i];
+            bx[xk(e) * LDX + xrow(e)] = rx[i];
         }
 #pragma unroll
         for (int i = 0; i < EY; ++i) {
             const int e = tid + NTHR * i;
-            const int c = YN ? e % NT : e / KT;
-            const int kk = YN ? e / NT : e % KT;
-            by[kk * LDY + c] = ry[i];
+            by[yk(e) * LDY + ycol(e)] = ry[i];
         }
-    };
-    auto compute = [&](int buf) {
-        const T* bx = sX + buf * L::XS + wm * S::WTM + (lane & 15);
-        const T* by = sY + buf * L::YS + wn * S::WTN + (lane & 15);
+    }
+};
+
+template <typename T, typename OffT>
+__device__ __forceinline__ void store_c(const KArgs<T, OffT>& a, OffT mm, OffT co, T acc) {
+    if (mm < a.m) {
+        const OffT o = a.rC[mm] + co;
+        T v = a.alpha * acc;
+        if (a.beta != T(0)) v += a.beta * a.C[o];
+        a.C[o] = v;
+    }
+}
+
+// Regular layout: a WM x WN grid of waves, each owning FM x FN fragments.
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
+struct TileRegular {
+    static constexpr int NTHR = WM * WN * 64;
+    static constexpr int WTM = MT / WM, WTN = NT / WN;
+    static constexpr int FM = WTM / 16, FN = WTN / 16;
+    static_assert(KT % 4 == 0, "KT must be a multiple of the MFMA depth");
+    static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tiles are made of 16x16 fragments");
+    typedef Pack<T, OffT, MT, NT, KT, NTHR, XM, YN> P;
+    static constexpr int SMEM = P::ELEMS;
+
+    static __device__ __forceinline__ void run(const KArgs<T, OffT>& a, int64_t tile, T* smem) {
+        typedef Mfma<T> M;
+        typedef typename M::acc_t acc_t;
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int wm = wave % WM, wn = wave / WM;
+        const int64_t tm = tile % a.tiles_m, tn = tile / a.tiles_m;
+        const OffT m0 = (OffT)(tm * MT), n0 = (OffT)(tn * NT);
+
+        P pk;
+        pk.init(a, m0, n0, tid);
+        acc_t acc[FM][FN];
 #pragma unroll
-        for (int s = 0; s < KT / 4; ++s) {
-            const int kr = 4 * s + (lane >> 4);
-            T fa[FM], fb[FN];
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int i = 0; i < FM; ++i) fa[i] = bx[kr * LDX + 16 * i];
+            for (int j = 0; j < FN; ++j)
 #pragma unroll
-            for (int j = 0; j < FN; ++j) fb[j] = by[kr * LDY + 16 * j];
+                for (int r = 0; r < 4; ++r) acc[i][j][r] = T(0);
+
+        const OffT nkb = (a.k + KT - 1) / KT;
+        if (nkb > 0) {
+            pk.load(a, 0, tid);
+            pk.store(smem, 0, tid);
+            __syncthreads();
+            for (OffT kb = 0; kb < nkb; ++kb) {
+                const int buf = (int)(kb & 1);
+                const bool more = kb + 1 < nkb;
+                if (more) pk.load(a, kb + 1, tid);
+                const T* bx = smem + buf * P::XS + wm * WTM + (lane & 15);
+                const T* by = smem + 2 * P::XS + buf * P::YS + wn * WTN + (lane & 15);
+#pragma unroll
+                for (int s = 0; s < KT / 4; ++s) {
+                    const int kr = 4 * s + (lane >> 4);
+                    T fa[FM], fb[FN];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) fa[i] = bx[kr * P::LDX + 16 * i];
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) fb[j] = by[kr * P::LDY + 16 * j];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) acc[i][j] = M::run(fa[i], fb[j], acc[i][j]);
+                }
+                if (more) pk.store(smem, buf ^ 1, tid);
+                __syncthreads();
+            }
+        }
+        // alpha/beta scatter-store through rscat_C / cscat_C (Sec. 6.1)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const OffT nn = n0 + wn * WTN + 16 * j + (lane & 15);
+            if (nn >= a.n) continue;
+            const OffT co = a.cC[nn];
 #pragma unroll
             for (int i = 0; i < FM; ++i)
 #pragma unroll
-                for (int j = 0; j < FN; ++j) acc[i][j] = M::run(fa[i], fb[j], acc[i][j]);
+                for (int r = 0; r < 4; ++r) store_c(a, (OffT)(m0 + wm * WTM + 16 * i + M::row(lane, r)), co, acc[i][j][r]);
         }
-    };
+    }
+};
 
-    if (nkb > 0) {
-        gload(0);
-        lstore(0);
-        __syncthreads();
-        for (OffT kb = 0; kb < nkb; ++kb) {
-            const int buf = (int)(kb & 1);
-            const bool more = kb + 1 < nkb;
-            if (more) gload(kb + 1);
-            compute(buf);
-            if (more) lstore(buf ^ 1);
-            __syncthreads();
+// Pinwheel layout for MT = NT = 144 on four waves: the 9 x 9 grid of 16 x 16
+// fragments is covered by four rectangles of 20 fragments (4x5 at (0,0), 5x4
+// at (0,5), 4x5 at (5,4), 5x4 at (4,0)) around the centre fragment (4,4),
+// whose k-steps are dealt round-robin to the four waves and summed in LDS at
+// the end.  Every SIMD then issues exactly 20.25 fragment updates per k-step,
+// and a 2304 x 2304 output is exactly 256 tiles, one per compute unit.
+template <typename T, typename OffT, int KT, bool XM, bool YN>
+struct TilePinwheel {
+    static constexpr int MT = 144, NT = 144, NTHR = 256;
+    static_assert(KT % 16 == 0, "the centre k-split needs KT a multiple of 16");
+    typedef Pack<T, OffT, MT, NT, KT, NTHR, XM, YN> P;
+    static constexpr int SMEM = P::ELEMS > 4 * 256 ? P::ELEMS : 4 * 256;
+
+    template <int R, int C>
+    static __device__ __forceinline__ void step(typename Mfma<T>::acc_t* acc, const T* bx, const T* by, int kr, int fr0,
+                                                int fc0) {
+        T fa[R], fb[C];
+#pragma unroll
+        for (int i = 0; i < R; ++i) fa[i] = bx[kr * P::LDX + 16 * (fr0 + i)];
+#pragma unroll
+        for (int j = 0; j < C; ++j) fb[j] = by[kr * P::LDY + 16 * (fc0 + j)];
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int j = 0; j < C; ++j) acc[i * C + j] = Mfma<T>::run(fa[i], fb[j], acc[i * C + j]);
+    }
+
+    template <int R, int C>
+    static __device__ __forceinline__ void epilogue(const KArgs<T, OffT>& a, const typename Mfma<T>::acc_t* acc,
+                                                    OffT m0, OffT n0, int fr0, int fc0, int lane) {
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const OffT nn = n0 + 16 * (fc0 + j) + (lane & 15);
+            if (nn >= a.n) continue;
+            const OffT co = a.cC[nn];
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    store_c(a, (OffT)(m0 + 16 * (fr0 + i) + Mfma<T>::row(lane, r)), co, acc[i * C + j][r]);
         }
     }
 
-    // alpha/beta scatter-store of the tile (Sec. 6.1: C tile written through
-    // rscat_C / cscat_C; C is read only when beta != 0)
+    static __device__ __forceinline__ void run(const KArgs<T, OffT>& a, int64_t tile, T* smem) {
+        typedef Mfma<T> M;
+        typedef typename M::acc_t acc_t;
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        // rectangle of this wave (in fragments)
+        const bool wide = (wave & 1) == 0;  // 4 x 5 for waves 0 and 2, 5 x 4 for 1 and 3
+        const int fr0 = wave == 2 ? 5 : wave == 3 ? 4 : 0;
+        const int fc0 = wave == 1 ? 5 : wave == 2 ? 4 : 0;
+        const int64_t tm = tile % a.tiles_m, tn = tile / a.tiles_m;
+        const OffT m0 = (OffT)(tm * MT), n0 = (OffT)(tn * NT);
+
+        P pk;
+        pk.init(a, m0, n0, tid);
+        acc_t acc[20], accc;
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-        const OffT nn = n0 + wn * S::WTN + 16 * j + (lane & 15);
-        if (nn >= a.n) continue;
-        const OffT co = a.cC[nn];
+        for (int f = 0; f < 20; ++f)
 #pragma unroll
-        for (int i = 0; i < FM; ++i) {
+            for (int r = 0; r < 4; ++r) acc[f][r] = T(0);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const OffT mm = m0 + wm * S::WTM + 16 * i + M::row(lane, r);
-                if (mm < a.m) {
-                    const OffT o = a.rC[mm] + co;
-                    T v = a.alpha * acc[i][j][r];
-                    if (a.beta != T(0)) v += a.beta * a.C[o];
-                    a.C[o] = v;
+        for (int r = 0; r < 4; ++r) accc[r] = T(0);
+
+        const OffT nkb = (a.k + KT - 1) / KT;
+        if (nkb > 0) {
+            pk.load(a, 0, tid);
+            pk.store(smem, 0, tid);
+            __syncthreads();
+            for (OffT kb = 0; kb < nkb; ++kb) {
+                const int buf = (int)(kb & 1);
+                const bool more = kb + 1 < nkb;
+                if (more) pk.load(a, kb + 1, tid);
+                const T* bx = smem + buf * P::XS + (lane & 15);
+                const T* by = smem + 2 * P::XS + buf * P::YS + (lane & 15);
+#pragma unroll
+                for (int s = 0; s < KT / 4; ++s) {
+                    const int kr = 4 * s + (lane >> 4);
+                    if (wide) step<4, 5>(acc, bx, by, kr, fr0, fc0);
+                    else step<5, 4>(acc, bx, by, kr, fr0, fc0);
+                    if ((s & 3) == wave) accc = M::run(bx[kr * P::LDX + 64], by[kr * P::LDY + 64], accc);
+                }
+                if (more) pk.store(smem, buf ^ 1, tid);
+                __syncthreads();
+            }
+        }
+        if (wide) epilogue<4, 5>(a, acc, m0, n0, fr0, fc0, lane);
+        else epilogue<5, 4>(a, acc, m0, n0, fr0, fc0, lane);
+        // centre fragment: partial sums of the four waves added in wave order
+#pragma unroll
+        for (int r = 0; r < 4; ++r) smem[wave * 256 + r * 64 + lane] = accc[r];
+        __syncthreads();
+        if (wave == 0) {
+            const OffT nn = n0 + 64 + (lane & 15);
+            if (nn < a.n) {
+                const OffT co = a.cC[nn];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    T v = smem[r * 64 + lane];
+                    v += smem[256 + r * 64 + lane];
+                    v += smem[512 + r * 64 + lane];
+                    v += smem[768 + r * 64 + lane];
+                    store_c(a, (OffT)(m0 + 64 + M::row(lane, r)), co, v);
                 }
             }
         }
     }
-}
+};
 
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT, bool XM, bool YN>
+struct TileOf {
+    typedef TileRegular<T, OffT, MT, NT, KT, WM, WN, XM, YN> type;
+    static constexpr int threads = WM * WN * 64;
+};
 template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
-__global__ __launch_bounds__(WM* WN * 64) void contract_kernel(KArgs<T, OffT> a) {
-    typedef Smem<T, MT, NT, KT, WM, WN, XM, YN> L;
-    __shared__ T smem[L::ELEMS];
-    tile_body<T, OffT, MT, NT, KT, WM, WN, XM, YN>(a, blockIdx.x, smem);
+struct TileOf<T, OffT, MT, NT, KT, WM, WN, 1, XM, YN> {
+    typedef TilePinwheel<T, OffT, KT, XM, YN> type;
+    static constexpr int threads = 256;
+};
+
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT, bool XM, bool YN>
+__global__ __launch_bounds__((TileOf<T, OffT, MT, NT, KT, WM, WN, LAYOUT, XM, YN>::threads)) void contract_kernel(
+    KArgs<T, OffT> a) {
+    typedef typename TileOf<T, OffT, MT, NT, KT, WM, WN, LAYOUT, XM, YN>::type Tile;
+    __shared__ T smem[Tile::SMEM];
+    Tile::run(a, blockIdx.x, smem);
 }
 
 // C := beta * C over the matrix view (k == 0 or alpha == 0).
@@ -283,19 +388,23 @@ static int hip_fail(hipError_t e, const char* what) {
     return TC_ERR_HIP;
 }
 
-template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN>
-static int launch_regular(const KArgs<T, OffT>& a, bool xm, bool yn, hipStream_t s) {
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT>
+static int launch_tile(const KArgs<T, OffT>& a, bool xm, bool yn, hipStream_t s) {
     const int64_t tiles = a.tiles_m * a.tiles_n;
     if (tiles <= 0) return TC_OK;
     if (tiles > 0x7fffffffLL) {
         set_error("too many tiles for one launch");
         return TC_ERR_ARG;
     }
-    dim3 grid((unsigned)tiles), block(WM * WN * 64);
-    if (xm && yn) hipLaunchKernelGGL((contract_kernel<T, OffT, MT, NT, KT, WM, WN, true, true>), grid, block, 0, s, a);
-    else if (xm) hipLaunchKernelGGL((contract_kernel<T, OffT, MT, NT, KT, WM, WN, true, false>), grid, block, 0, s, a);
-    else if (yn) hipLaunchKernelGGL((contract_kernel<T, OffT, MT, NT, KT, WM, WN, false, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((contract_kernel<T, OffT, MT, NT, KT, WM, WN, false, false>), grid, block, 0, s, a);
+    dim3 grid((unsigned)tiles), block(TileOf<T, OffT, MT, NT, KT, WM, WN, LAYOUT, true, true>::threads);
+    if (xm && yn)
+        hipLaunchKernelGGL((contract_kernel<T, OffT, MT, NT, KT, WM, WN, LAYOUT, true, true>), grid, block, 0, s, a);
+    else if (xm)
+        hipLaunchKernelGGL((contract_kernel<T, OffT, MT, NT, KT, WM, WN, LAYOUT, true, false>), grid, block, 0, s, a);
+    else if (yn)
+        hipLaunchKernelGGL((contract_kernel<T, OffT, MT, NT, KT, WM, WN, LAYOUT, false, true>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((contract_kernel<T, OffT, MT, NT, KT, WM, WN, LAYOUT, false, false>), grid, block, 0, s, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? TC_OK : hip_fail(e, "kernel launch");
 }
@@ -336,7 +445,7 @@ static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, co
     const bool xm = p.x_lanes_m, yn = p.y_lanes_n;
 #define TC_CASE(id, MT, NT, KT, WM, WN, L) \
     case id:                               \
-        return launch_regular<T, OffT, MT, NT, KT, WM, WN>(a, xm, yn, s);
+        return launch_tile<T, OffT, MT, NT, KT, WM, WN, L>(a, xm, yn, s);
     if (p.dtype == TC_F64) {
         switch (p.tile) { TC_TILES_F64(TC_CASE) }
     } else {

@@ -14,13 +14,15 @@
     X(0, 32, 32, 16, 1, 1, 0)      \
     X(1, 64, 64, 16, 2, 2, 0)      \
     X(2, 128, 64, 16, 2, 2, 0)     \
-    X(3, 128, 128, 16, 2, 2, 0)
+    X(3, 128, 128, 16, 2, 2, 0)    \
+    X(4, 144, 144, 16, 1, 1, 1)
 
 #define TC_TILES_F32(X)            \
     X(0, 32, 32, 32, 1, 1, 0)      \
     X(1, 64, 64, 32, 2, 2, 0)      \
     X(2, 128, 64, 32, 2, 2, 0)     \
-    X(3, 128, 128, 32, 2, 2, 0)
+    X(3, 128, 128, 32, 2, 2, 0)    \
+    X(4, 144, 144, 32, 1, 1, 1)
 
 // split-bf16: KT is a multiple of the bf16 MFMA depth (32)
 #define TC_TILES_BF16X3(X)         \

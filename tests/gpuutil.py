@@ -23,7 +23,7 @@ def to_dev(a, dtype=None):
     base = torch.zeros(max(span, 1), dtype=torch.from_numpy(np.zeros(1, a.dtype)).dtype, device="cuda")
     t = torch.as_strided(base, a.shape, strides)
     if a.size:
-        t.copy_(torch.from_numpy(np.ascontiguousarray(a)).to("cuda"))
+        t.copy_(torch.from_numpy(np.ascontiguousarray(a).reshape(a.shape)).to("cuda"))
     return t
 
 

@@ -193,7 +193,7 @@ def test_noncontiguous_views(oracle_mod):
     big = inputs.colmajor_from_flat(rng.uniform(-1, 1, 40 * 9 * 30), (40, 9, 30))
     A = big[3:35:2, 1:8, ::3]        # a[16] x b[7] x p[10] with gaps
     B = np.asfortranarray(rng.uniform(-1, 1, (10, 13)))[:, ::2]  # p x j[7]
-    C = inputs.colmajor((7, 16, 7), fill=0.0)  # j b a -> labels "jba"
+    C = inputs.colmajor((7, 7, 16), fill=0.0)  # j[7] b[7] a[16]
     p = inputs.Problem("abp", "pj", "jba", A, B, C, 1.0, 0.0, "views",
                        {"a": 16, "b": 7, "p": 10, "j": 7})
     check_fp64(oracle_mod, p, gpu_result(p))
