@@ -254,8 +254,13 @@ int build_plan(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, in
     if (p->noop) p->m = p->n = 0;
 
     // --- offsets width ------------------------------------------------------
+    // 32-bit offsets need element spans below 2^31; the 32-bit kernels also
+    // address A and B with bounds-checked buffer loads whose byte offsets
+    // must stay below 2^31.
     const int64_t lim = (int64_t)0x7fffffff;
-    p->off64 = p->spanA > lim || p->spanB > lim || p->spanC > lim || p->m > lim || p->n > lim || p->k > lim;
+    const int64_t elt = dtype == TC_F64 ? 8 : 4;
+    p->off64 = p->spanA * elt > lim || p->spanB * elt > lim || p->spanC > lim || p->m > lim || p->n > lim ||
+               p->k > lim;
 
     // --- scatter vectors (Sec. 6.1) --------------------------------------
     if (!p->noop) {

@@ -7,7 +7,8 @@
 //   LAYOUT   0 = regular wave grid; 1 = "pinwheel": 4 waves on a 9x9 grid of
 //            16x16 fragments, four 4x5 / 5x4 rectangles around the centre
 //            fragment whose k-range is split over the 4 waves, so that every
-//            SIMD does exactly 20.25 fragments of work
+//            SIMD does exactly 20.25 fragments of work; 2 = the same on 8
+//            waves (two per SIMD), each owning half a rectangle
 #pragma once
 
 #define TC_TILES_F64(X)            \
@@ -15,7 +16,8 @@
     X(1, 64, 64, 16, 2, 2, 0)      \
     X(2, 128, 64, 16, 2, 2, 0)     \
     X(3, 128, 128, 16, 2, 2, 0)    \
-    X(4, 144, 144, 16, 1, 1, 1)
+    X(4, 144, 144, 16, 1, 1, 1)    \
+    X(5, 144, 144, 16, 1, 1, 2)
 
 #define TC_TILES_F32(X)            \
     X(0, 32, 32, 32, 1, 1, 0)      \
@@ -35,7 +37,7 @@ namespace tc {
 
 struct TileCfg {
     int MT, NT, KT, WM, WN, layout;
-    int waves() const { return layout == 1 ? 4 : WM * WN; }
+    int waves() const { return layout == 1 ? 4 : layout == 2 ? 8 : WM * WN; }
 };
 
 #define TC_TILE_ENTRY(id, MT, NT, KT, WM, WN, L) TileCfg{MT, NT, KT, WM, WN, L},
