@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "tiles.hpp"):
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1607_00291_amd", "csrc"))):
         with open(os.path.join(ROOT, "paper_1607_00291_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

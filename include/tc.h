@@ -173,8 +173,22 @@ int tc_batch_create(tc_batch** batch, int count, const tc_plan* const* plans, co
                     const void* const* A, const void* const* B, const double* beta, void* const* C);
 int tc_batch_execute(const tc_batch* batch, void* stream);
 int tc_batch_destroy(tc_batch* batch);
-/* Work-item count and the tile configuration the batch launch uses. */
+/* Work-item count, the tile configuration and the persistent grid size of
+ * the batch launch.  Problems are laid out in decreasing order of k (the cost
+ * of one tile) so that the workgroups' static stride over the work list is
+ * balanced.  One tile configuration serves the whole batch; all regular
+ * configurations of a dtype share KT, so each output element is summed in
+ * the same order as by tc_plan_execute with a regular tile (bitwise equal). */
 int tc_batch_info(const tc_batch* batch, int64_t* work_items, int* tile, int* grid);
+/* Change the batch's tile configuration (regular layouts only); re-uploads
+ * the work table (synchronous, not during capture). */
+int tc_batch_set_tile(tc_batch* batch, int tile);
+/* Autotuner for batches: times the whole batch launch (reps runs after one
+ * warm-up, hipEvent timing on `stream`) under every regular tile
+ * configuration and keeps the fastest.  Runs the batch (1 + reps) times per
+ * configuration, so outputs with beta != 0 are updated repeatedly: tune on
+ * scratch outputs.  Synchronises `stream`.  *best_ms may be NULL. */
+int tc_batch_autotune(tc_batch* batch, int reps, void* stream, double* best_ms);
 
 /*
  * Building blocks of the block-scatter-matrix layout, exported for tests and

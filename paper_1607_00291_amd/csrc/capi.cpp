@@ -24,6 +24,8 @@ struct tc_batch {
     int dtype = 0, mode = 0, tile = 0, count = 0, device = 0, grid = 0;
     bool off64 = false;
     int64_t total_items = 0;
+    std::vector<tc::BatchItemDev> host;  // per problem, in launch order (device pointers filled)
+    std::vector<int> order;              // problem index of each table entry
     void* table = nullptr;    // device BatchItemDev[count]
     void* vectors = nullptr;  // device arena holding every problem's vectors
 };
@@ -418,25 +420,276 @@ int tc_contract(double alpha, const void* A, int ndim_A, const int64_t* lens_A, 
     }
 }
 
+}  // extern "C"
+
+namespace tc {
+
+// Work-item counts and prefix sums of a batch for its current tile, then the
+// table upload.  Problems are ordered by decreasing k (the cost of one tile),
+// so that the static stride assignment of the persistent kernel is balanced.
+static int batch_layout(tc_batch* b) {
+    const TileCfg& t = tile_table(b->dtype, b->mode)[b->tile];
+    std::vector<int> idx(b->host.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    std::vector<BatchItemDev> items = b->host;
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return items[x].k > items[y].k; });
+    std::vector<BatchItemDev> table;
+    table.reserve(items.size());
+    int64_t first = 0;
+    for (int i : idx) {
+        BatchItemDev it = items[i];
+        it.tiles_m = (it.m + t.MT - 1) / t.MT;
+        it.tiles_n = (it.n + t.NT - 1) / t.NT;
+        it.first_item = first;
+        first += it.tiles_m * it.tiles_n;
+        table.push_back(it);
+    }
+    b->order = idx;
+    b->total_items = first;
+    if (!b->table) {
+        hipError_t e = hipMalloc(&b->table, std::max<size_t>(table.size(), 1) * sizeof(BatchItemDev));
+        if (e != hipSuccess) {
+            b->table = nullptr;
+            set_error("hipMalloc of the batch table failed");
+            return TC_ERR_NOMEM;
+        }
+    }
+    if (!table.empty()) {
+        hipError_t e = hipMemcpy(b->table, table.data(), table.size() * sizeof(BatchItemDev), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hipfail(e, "hipMemcpy of the batch table");
+    }
+    b->grid = batch_grid(b->dtype, b->mode, b->tile, b->off64, b->total_items);
+    if (b->total_items > 0 && b->grid <= 0) {
+        set_error("could not size the persistent grid");
+        return TC_ERR_HIP;
+    }
+    return TC_OK;
+}
+
+static int batch_create(tc_batch** out, int count, const tc_plan* const* plans, const double* alpha,
+                        const void* const* A, const void* const* B, const double* beta, void* const* C) {
+    if (!out) {
+        set_error("batch out-pointer is NULL");
+        return TC_ERR_NULL;
+    }
+    *out = nullptr;
+    if (count < 0) {
+        set_error("negative problem count");
+        return TC_ERR_ARG;
+    }
+    if (count > 0 && (!plans || !alpha || !A || !B || !beta || !C)) {
+        set_error("NULL batch argument array");
+        return TC_ERR_NULL;
+    }
+    int dtype = TC_F64, mode = TC_NATIVE;
+    bool off64 = false;
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i]) {
+            set_error("NULL plan in batch");
+            return TC_ERR_NULL;
+        }
+        const Plan& p = *plans[i]->p;
+        if (i == 0) {
+            dtype = p.dtype;
+            mode = p.mode;
+        } else if (p.dtype != dtype || p.mode != mode) {
+            set_error("all problems of a batch need the same dtype and mode");
+            return TC_ERR_DTYPE;
+        }
+        off64 |= p.off64;
+    }
+    if (mode != TC_NATIVE) {
+        set_error("batched launches support the native modes");
+        return TC_ERR_DTYPE;
+    }
+    const size_t w = off64 ? 8 : 4, elt = elt_size(dtype);
+    // per-problem checks (as tc_plan_execute) and arena layout
+    std::vector<size_t> base(count, 0);
+    size_t total = 0;
+    auto al = [](size_t n) { return (std::max<size_t>(n, 1) + 63) & ~(size_t)63; };
+    for (int i = 0; i < count; ++i) {
+        const Plan& p = *plans[i]->p;
+        if (p.noop || p.m == 0 || p.n == 0) continue;
+        const bool reads_ab = !(p.k_empty || alpha[i] == 0.0);
+        if (!C[i] || (reads_ab && (!A[i] || !B[i]))) {
+            set_error("NULL tensor pointer in batch problem " + std::to_string(i));
+            return TC_ERR_NULL;
+        }
+        if (overlaps(C[i], p.spanC, A[i], p.spanA, elt) || overlaps(C[i], p.spanC, B[i], p.spanB, elt)) {
+            set_error("C overlaps A or B in batch problem " + std::to_string(i));
+            return TC_ERR_ALIAS;
+        }
+        base[i] = total;
+        total += al(p.rX.size()) + al(p.cX.size()) + al(p.rY.size()) + al(p.cY.size()) + al(p.rC.size()) +
+                 al(p.cC.size()) + al(p.kbsX.size()) + al(p.kbsY.size());
+    }
+    auto b = std::make_unique<tc_batch>();
+    b->dtype = dtype;
+    b->mode = mode;
+    b->count = count;
+    b->off64 = off64;
+    hipGetDevice(&b->device);
+    std::vector<char> host(std::max<size_t>(total, 1) * w, 0);
+    if (total) {
+        hipError_t e = hipMalloc(&b->vectors, host.size());
+        if (e != hipSuccess) {
+            b->vectors = nullptr;
+            set_error("hipMalloc of the batch vectors failed");
+            return TC_ERR_NOMEM;
+        }
+    }
+    const char* dbase = (const char*)b->vectors;
+    for (int i = 0; i < count; ++i) {
+        const Plan& p = *plans[i]->p;
+        if (p.noop || p.m == 0 || p.n == 0) continue;
+        const std::vector<int64_t>* vecs[8] = {&p.rX, &p.cX, &p.rY, &p.cY, &p.rC, &p.cC, &p.kbsX, &p.kbsY};
+        const void* ptrs[8];
+        size_t o = base[i];
+        for (int v = 0; v < 8; ++v) {
+            for (size_t j = 0; j < vecs[v]->size(); ++j) {
+                if (off64) ((int64_t*)host.data())[o + j] = (*vecs[v])[j];
+                else ((int32_t*)host.data())[o + j] = (int32_t)(*vecs[v])[j];
+            }
+            ptrs[v] = dbase + o * w;
+            o += al(vecs[v]->size());
+        }
+        const bool scale_only = p.k_empty || alpha[i] == 0.0;
+        BatchItemDev it{};
+        it.X = p.swapped ? B[i] : A[i];
+        it.Y = p.swapped ? A[i] : B[i];
+        it.C = C[i];
+        it.rX = ptrs[0];
+        it.cX = ptrs[1];
+        it.rY = ptrs[2];
+        it.cY = ptrs[3];
+        it.rC = ptrs[4];
+        it.cC = ptrs[5];
+        it.kbsX = ptrs[6];
+        it.kbsY = ptrs[7];
+        it.m = p.m;
+        it.n = p.n;
+        it.k = scale_only ? 0 : p.k;
+        it.spanX = p.swapped ? p.spanB : p.spanA;
+        it.spanY = p.swapped ? p.spanA : p.spanB;
+        it.alpha = alpha[i];
+        it.beta = beta[i];
+        it.x_lanes_m = p.x_lanes_m;
+        it.y_lanes_n = p.y_lanes_n;
+        b->host.push_back(it);
+    }
+    if (total) {
+        hipError_t e = hipMemcpy(b->vectors, host.data(), total * w, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            tc_batch_destroy(b.release());
+            return hipfail(e, "hipMemcpy of the batch vectors");
+        }
+    }
+    b->tile = 1 < tile_count(dtype, mode) ? 1 : 0;  // 64 x 64 until tuned
+    int st = batch_layout(b.get());
+    if (st) {
+        tc_batch_destroy(b.release());
+        return st;
+    }
+    *out = b.release();
+    return TC_OK;
+}
+
+}  // namespace tc
+
+extern "C" {
+
 int tc_batch_create(tc_batch** batch, int count, const tc_plan* const* plans, const double* alpha,
                     const void* const* A, const void* const* B, const double* beta, void* const* C) {
-    (void)count;
-    (void)plans;
-    (void)alpha;
-    (void)A;
-    (void)B;
-    (void)beta;
-    (void)C;
-    if (batch) *batch = nullptr;
-    set_error("batched contractions are not built into this library");
-    return TC_ERR_ARG;
+    try {
+        return batch_create(batch, count, plans, alpha, A, B, beta, C);
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory");
+        return TC_ERR_NOMEM;
+    } catch (...) {
+        set_error("internal error while building the batch");
+        return TC_ERR_ARG;
+    }
 }
 
 int tc_batch_execute(const tc_batch* batch, void* stream) {
-    (void)batch;
-    (void)stream;
-    set_error("batched contractions are not built into this library");
-    return TC_ERR_ARG;
+    if (!batch) {
+        set_error("batch is NULL");
+        return TC_ERR_NULL;
+    }
+    if (batch->total_items == 0) return TC_OK;
+    int dev = 0;
+    hipGetDevice(&dev);
+    if (dev != batch->device) {
+        set_error("batch executed on a device other than the one it was created on");
+        return TC_ERR_ARG;
+    }
+    return launch_batch(batch->dtype, batch->mode, batch->tile, batch->off64, (const BatchItemDev*)batch->table,
+                        (int)batch->host.size(), batch->total_items, batch->grid, (hipStream_t)stream);
+}
+
+int tc_batch_set_tile(tc_batch* batch, int tile) {
+    if (!batch) {
+        set_error("batch is NULL");
+        return TC_ERR_NULL;
+    }
+    if (tile < 0 || tile >= tile_count(batch->dtype, batch->mode) ||
+        tile_table(batch->dtype, batch->mode)[tile].layout != 0) {
+        set_error("not a regular tile configuration of this dtype/mode");
+        return TC_ERR_ARG;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(nullptr, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+        set_error("changing a batch's tile uploads its table: not allowed during capture");
+        return TC_ERR_CAPTURE;
+    }
+    batch->tile = tile;
+    return batch_layout(batch);
+}
+
+int tc_batch_autotune(tc_batch* batch, int reps, void* stream, double* best_ms) {
+    if (!batch) {
+        set_error("batch is NULL");
+        return TC_ERR_NULL;
+    }
+    if (reps < 1) reps = 1;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return hipfail(e, "hipEventCreate");
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        hipEventDestroy(e0);
+        return hipfail(e, "hipEventCreate");
+    }
+    int best = batch->tile, st = TC_OK;
+    float best_t = 1e30f;
+    const int nt = tile_count(batch->dtype, batch->mode);
+    for (int t = 0; t < nt && st == TC_OK; ++t) {
+        if (tile_table(batch->dtype, batch->mode)[t].layout != 0) continue;
+        if ((st = tc_batch_set_tile(batch, t))) break;
+        if ((st = tc_batch_execute(batch, s))) break;  // warm-up
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == TC_OK; ++r) st = tc_batch_execute(batch, s);
+        hipEventRecord(e1, s);
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) {
+            st = hipfail(e, "batch autotune timing");
+            break;
+        }
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (ms < best_t) {
+            best_t = ms;
+            best = t;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    int st2 = tc_batch_set_tile(batch, best);
+    if (st) return st;
+    if (st2) return st2;
+    if (best_ms) *best_ms = best_t;
+    return TC_OK;
 }
 
 int tc_batch_destroy(tc_batch* batch) {

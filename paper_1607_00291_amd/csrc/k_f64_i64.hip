@@ -1,0 +1,17 @@
+// Instantiation of the contraction and batched kernels for one storage type
+// and one offset width (one translation unit each, compiled in parallel).
+#include "kernels_impl.hpp"
+
+namespace tc {
+
+int launch_typed_f64_i64(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
+                       void* C, hipStream_t s) {
+    return launch_typed<double, int64_t>(p, dv, alpha, A, B, beta, C, s);
+}
+
+int batch_dispatch_f64_i64(int dtype, int tile, bool launch, const BatchItemDev* items, int count, int64_t total, int grid,
+                         hipStream_t s) {
+    return batch_dispatch<double, int64_t>(dtype, tile, launch, items, count, total, grid, s);
+}
+
+}  // namespace tc

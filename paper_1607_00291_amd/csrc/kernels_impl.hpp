@@ -1,0 +1,909 @@
+#pragma once
+// Kernel templates of the transpose-free contraction (block-scatter-matrix
+// tensor contraction, Sec. 6.2) and their launchers.
+//
+// One workgroup computes one MT x NT tile of the matrix view C[m, n] of the
+// output.  Its K loop runs over LDS stages of depth KT:
+//   pack   : every thread gathers its share of the MT x KT sliver of X and
+//            the KT x NT sliver of Y straight from the tensors' own layouts,
+//            element (m, k) of X at X + rscat_X[m] + cscat_X[k] (Sec. 6.1).
+//            The per-thread row / column offsets are loaded once per tile;
+//            the k offsets come from the block stride of the current k block
+//            when it is valid (Sec. 6.2, the k_P blocking) and from the
+//            scatter vector otherwise.  Lanes run along each operand's
+//            unit-stride index, so global reads coalesce whatever the
+//            permutation of the tensor's dimensions.  The stage is written
+//            to LDS in the k-major order the matrix-core fragments read,
+//            which is where the tensor-to-matrix reshape is folded in.
+//   micro  : waves run 16x16x4 matrix-core instructions on register tiles
+//            (FP64 or FP32 accumulation in the storage type).
+//   store  : accumulators are scaled by alpha and written to
+//            C + rscat_C[m] + cscat_C[n], reading C only when beta != 0.
+// LDS is double-buffered: global loads for stage s+1 are in flight while the
+// matrix cores consume stage s; one barrier per stage.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "launch.hpp"
+#include "tc.h"
+#include "tiles.hpp"
+
+namespace tc {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Four FP64 accumulators kept as independent scalars, so every matrix-core
+// instruction can update its accumulator in place.
+struct f64acc {
+    double v[4];
+    __device__ __forceinline__ double& operator[](int i) { return v[i]; }
+    __device__ __forceinline__ const double& operator[](int i) const { return v[i]; }
+};
+
+// Matrix-core update of one 16 x 16 output fragment by a 16 x 4 sliver of X
+// and a 4 x 16 sliver of Y, both read from k-major LDS stages.  Each trait
+// gives the operand loads, the update, and the (row, column) inside the
+// fragment of accumulator element t of a lane.
+template <typename T>
+struct Mfma;
+
+// FP64: four v_mfma_f64_4x4x4_4b per fragment update.  One such instruction
+// holds four independent 4x4x4 blocks; lane l = i + 4*blk + 16*k carries
+// A[blk][i][k] and B[blk][k][j = l%4], and receives D[blk][i = l/16][j = l%4]
+// at l = j + 4*blk + 16*i.  Instruction t pairs A rows 4*blk.. with B columns
+// 4*((blk + t) % 4).., so the four instructions cover the whole 16 x 16
+// fragment with one shared A register and four B registers.  (On gfx950 this
+// form issues at close to the FP64 matrix peak; the 16x16x4 FP64 form
+// sustains about half of it.)
+template <>
+struct Mfma<double> {
+    typedef f64acc acc_t;
+    typedef double afrag;
+    struct bfrag {
+        double v[4];
+    };
+    static __device__ __forceinline__ int bcol(int lane, int t) { return 4 * ((((lane >> 2) & 3) + t) & 3) + (lane & 3); }
+    static __device__ __forceinline__ afrag load_a(const double* row, int lane) { return row[lane & 15]; }
+    static __device__ __forceinline__ bfrag load_b(const double* row, int lane) {
+        bfrag f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) f.v[t] = row[bcol(lane, t)];
+        return f;
+    }
+    static __device__ __forceinline__ void run(afrag a, const bfrag& b, acc_t& c) {
+        c.v[0] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b.v[0], c.v[0], 0, 0, 0);
+        c.v[1] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b.v[1], c.v[1], 0, 0, 0);
+        c.v[2] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b.v[2], c.v[2], 0, 0, 0);
+        c.v[3] = __builtin_amdgcn_mfma_f64_4x4x4f64(a, b.v[3], c.v[3], 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int) { return 4 * ((lane >> 2) & 3) + (lane >> 4); }
+    static __device__ __forceinline__ int col(int lane, int t) { return bcol(lane, t); }
+};
+
+// FP64 with the diagonal on the A side: instruction t pairs B columns
+// 4*blk.. with A rows 4*((blk + t) % 4).., so one B register is shared and
+// four A registers are read.  Used where a wave holds more B fragments than
+// A fragments (fewer operand registers live).
+struct Mfma64DiagA {
+    typedef f64acc acc_t;
+    struct afrag {
+        double v[4];
+    };
+    typedef double bfrag;
+    static __device__ __forceinline__ afrag load_a(const double* row, int lane) {
+        afrag f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) f.v[t] = row[Mfma<double>::bcol(lane, t)];
+        return f;
+    }
+    static __device__ __forceinline__ bfrag load_b(const double* row, int lane) { return row[lane & 15]; }
+    static __device__ __forceinline__ void run(const afrag& a, bfrag b, acc_t& c) {
+        c.v[0] = __builtin_amdgcn_mfma_f64_4x4x4f64(a.v[0], b, c.v[0], 0, 0, 0);
+        c.v[1] = __builtin_amdgcn_mfma_f64_4x4x4f64(a.v[1], b, c.v[1], 0, 0, 0);
+        c.v[2] = __builtin_amdgcn_mfma_f64_4x4x4f64(a.v[2], b, c.v[2], 0, 0, 0);
+        c.v[3] = __builtin_amdgcn_mfma_f64_4x4x4f64(a.v[3], b, c.v[3], 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int t) { return Mfma<double>::bcol(lane, t) - (lane & 3) + (lane >> 4); }
+    static __device__ __forceinline__ int col(int lane, int) { return lane & 15; }
+};
+
+// Operand schedule for a wave rectangle of R x C fragments: FP64 puts the
+// diagonal on the side with fewer fragments.
+template <typename T, bool WIDE>
+struct MfmaFor {
+    typedef Mfma<T> type;
+};
+template <>
+struct MfmaFor<double, true> {
+    typedef Mfma64DiagA type;
+};
+
+// FP32: v_mfma_f32_16x16x4_f32; lane l carries A[l%16][l/16], B[l/16][l%16]
+// and receives D[4*(l/16) + t][l%16] in element t.
+template <>
+struct Mfma<float> {
+    typedef f32x4 acc_t;
+    typedef float afrag;
+    typedef float bfrag;
+    static __device__ __forceinline__ afrag load_a(const float* row, int lane) { return row[lane & 15]; }
+    static __device__ __forceinline__ bfrag load_b(const float* row, int lane) { return row[lane & 15]; }
+    static __device__ __forceinline__ void run(afrag a, bfrag b, acc_t& c) {
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int t) { return 4 * (lane >> 4) + t; }
+    static __device__ __forceinline__ int col(int lane, int) { return lane & 15; }
+};
+
+template <typename T, typename OffT>
+struct KArgs {
+    const T* X;
+    const T* Y;
+    T* C;
+    const OffT* rX;
+    const OffT* cX;
+    const OffT* rY;
+    const OffT* cY;
+    const OffT* rC;
+    const OffT* cC;
+    const OffT* kbsX;
+    const OffT* kbsY;
+    OffT m, n, k;
+    int64_t tiles_m, tiles_n;
+    int64_t spanX, spanY;  // element spans of X and Y (bounds of the buffer loads)
+    T alpha, beta;
+};
+
+// LDS row pitch (in elements) of a k-major stage: one element of padding when
+// the lanes of the gather run along k (consecutive lanes then write to
+// consecutive LDS rows, and the pad spreads them over the banks).
+template <int W, bool LANES_ALONG_ROW>
+struct Pitch {
+    static constexpr int value = LANES_ALONG_ROW ? W : W + 1;
+};
+
+// Bounds-checked buffer loads (32-bit-offset plans): a byte offset at or past
+// the buffer's size reads 0, so ragged edges need no select after the load
+// and every load of a stage can stay in flight until the LDS write.
+#define TC_BUF_DWORD3 0x00020000
+static constexpr uint32_t kOutOfRange = 0x80000000u;
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const T* p, int64_t elems) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)(elems * (int64_t)sizeof(T)), TC_BUF_DWORD3);
+}
+template <typename T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
+// The pack stage of one operand of one tile: an R x KT sliver (R rows of m
+// for X, of n for Y) gathered through the offset vectors into registers, then
+// written to a k-major LDS stage.  Element e = t + NTHR * i of a stage is
+// (row, kk) with the row index fastest when the operand's lanes run along its
+// free index (LR), and kk fastest when they run along k.
+template <typename T, typename OffT, int R, int KT, int NTHR, bool LR>
+struct PackOp {
+    static constexpr int E = R * KT / NTHR;
+    static constexpr int LD = Pitch<R, LR>::value;
+    static constexpr int S = KT * LD;  // elements of one stage
+    static_assert((R * KT) % NTHR == 0, "stage must split evenly over threads");
+
+    static __device__ __forceinline__ int ridx(int e) { return LR ? e % R : e / KT; }
+    static __device__ __forceinline__ int kidx(int e) { return LR ? e / R : e % KT; }
+
+    OffT o[E];  // offsets of this thread's rows, fixed per tile; -1 past the edge
+    T r[E];     // one stage in flight
+
+    __device__ __forceinline__ void init(const OffT* rowvec, OffT r0, OffT rmax, int t) {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const OffT rr = r0 + ridx(t + NTHR * i);
+            const OffT x = rowvec[rr < rmax ? rr : rmax - 1];
+            o[i] = rr < rmax ? x : OffT(-1);
+        }
+    }
+
+    // Global gather of k block kb.  A valid block stride (Sec. 6.2) replaces
+    // the per-element scatter-vector reads along k; the choice is uniform.
+    __device__ __forceinline__ void load(const T* base, int64_t span, const OffT* kvec, const OffT* kbs, OffT kb, OffT K,
+                                         int t) {
+        const OffT k0 = kb * KT;
+        const OffT sk = kbs[kb];
+        OffT ko[E];
+        OffT kbase = 0;
+        if (sk) {
+            kbase = kvec[k0];
+#pragma unroll
+            for (int i = 0; i < E; ++i) ko[i] = (OffT)kidx(t + NTHR * i) * sk;
+        } else {
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const OffT kg = k0 + kidx(t + NTHR * i);
+                ko[i] = kvec[kg < K ? kg : K - 1];
+            }
+        }
+        if constexpr (sizeof(OffT) == 4) {
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, span);
+            const uint32_t soff = (uint32_t)kbase * (uint32_t)sizeof(T);
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const bool ok = o[i] >= 0 && k0 + kidx(t + NTHR * i) < K;
+                const uint32_t vo = ok ? (uint32_t)(o[i] + ko[i]) * (uint32_t)sizeof(T) : kOutOfRange;
+                r[i] = buf_load<T>(rs, vo, soff);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const bool ok = o[i] >= 0 && k0 + kidx(t + NTHR * i) < K;
+                const T x = base[ok ? kbase + o[i] + ko[i] : OffT(0)];
+                r[i] = ok ? x : T(0);
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(T* stage, int t) const {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int e = t + NTHR * i;
+            stage[kidx(e) * LD + ridx(e)] = r[i];
+        }
+    }
+};
+
+// Both operands of a tile, every thread gathering its share of each.
+template <typename T, typename OffT, int MT, int NT, int KT, int NTHR, bool XM, bool YN>
+struct Pack {
+    typedef PackOp<T, OffT, MT, KT, NTHR, XM> PX;
+    typedef PackOp<T, OffT, NT, KT, NTHR, YN> PY;
+    static constexpr int LDX = PX::LD, LDY = PY::LD, XS = PX::S, YS = PY::S;
+    static constexpr int ELEMS = 2 * (XS + YS);  // [X0][X1][Y0][Y1]
+    PX px;
+    PY py;
+    __device__ __forceinline__ void init(const KArgs<T, OffT>& a, OffT m0, OffT n0, int t) {
+        px.init(a.rX, m0, a.m, t);
+        py.init(a.cY, n0, a.n, t);
+    }
+    __device__ __forceinline__ void load(const KArgs<T, OffT>& a, OffT kb, int t) {
+        px.load(a.X, a.spanX, a.cX, a.kbsX, kb, a.k, t);
+        py.load(a.Y, a.spanY, a.rY, a.kbsY, kb, a.k, t);
+    }
+    __device__ __forceinline__ void store(T* smem, int buf, int t) const {
+        px.store(smem + buf * XS, t);
+        py.store(smem + 2 * XS + buf * YS, t);
+    }
+};
+
+// alpha/beta update of one output element through rscat_C / cscat_C
+// (Sec. 6.1); C is read only when beta != 0.
+template <typename T, typename OffT>
+__device__ __forceinline__ void store_c(const KArgs<T, OffT>& a, OffT mm, OffT nn, T acc) {
+    if (mm < a.m && nn < a.n) {
+        const OffT o = a.rC[mm] + a.cC[nn];
+        T v = a.alpha * acc;
+        if (a.beta != T(0)) v += a.beta * a.C[o];
+        a.C[o] = v;
+    }
+}
+
+// Store every element of one accumulator fragment whose origin in C's matrix
+// view is (fm0, fn0).
+template <typename T, typename OffT, typename M = Mfma<T>>
+__device__ __forceinline__ void store_frag(const KArgs<T, OffT>& a, OffT fm0, OffT fn0, const typename M::acc_t& acc,
+                                           int lane) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) store_c(a, (OffT)(fm0 + M::row(lane, t)), (OffT)(fn0 + M::col(lane, t)), acc[t]);
+}
+
+// One k-step (depth 4) of an R x C rectangle of fragments whose origin is
+// fragment (fr0, fc0); bx / by point at LDS row kr of the X / Y stage.
+template <typename T, typename M, int R, int C>
+__device__ __forceinline__ void rect_step(typename M::acc_t* acc, const T* bx, const T* by, int fr0, int fc0, int lane) {
+    typename M::afrag fa[R];
+    typename M::bfrag fb[C];
+#pragma unroll
+    for (int i = 0; i < R; ++i) fa[i] = M::load_a(bx + 16 * (fr0 + i), lane);
+#pragma unroll
+    for (int j = 0; j < C; ++j) fb[j] = M::load_b(by + 16 * (fc0 + j), lane);
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < C; ++j) M::run(fa[i], fb[j], acc[i * C + j]);
+}
+
+template <typename T, typename OffT, typename M, int R, int C>
+__device__ __forceinline__ void rect_store(const KArgs<T, OffT>& a, const typename M::acc_t* acc, OffT m0, OffT n0,
+                                           int fr0, int fc0, int lane) {
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < C; ++j)
+            store_frag<T, OffT, M>(a, (OffT)(m0 + 16 * (fr0 + i)), (OffT)(n0 + 16 * (fc0 + j)), acc[i * C + j], lane);
+}
+
+// Store of a rectangle computed as C^T: fragment (i, j) covers n-fragment
+// fp0 + i and m-fragment fq0 + j; its element rows are n, columns m.
+template <typename T, typename OffT, typename M, int R, int C>
+__device__ __forceinline__ void rect_store_t(const KArgs<T, OffT>& a, const typename M::acc_t* acc, OffT m0, OffT n0,
+                                             int fp0, int fq0, int lane) {
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < C; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                store_c(a, (OffT)(m0 + 16 * (fq0 + j) + M::col(lane, t)), (OffT)(n0 + 16 * (fp0 + i) + M::row(lane, t)),
+                        acc[i * C + j][t]);
+}
+
+// Regular layout: a WM x WN grid of waves, each owning FM x FN fragments.
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
+struct TileRegular {
+    static constexpr int NTHR = WM * WN * 64;
+    static constexpr int WTM = MT / WM, WTN = NT / WN;
+    static constexpr int FM = WTM / 16, FN = WTN / 16;
+    static_assert(KT % 4 == 0, "KT must be a multiple of the MFMA depth");
+    static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tiles are made of 16x16 fragments");
+    typedef Pack<T, OffT, MT, NT, KT, NTHR, XM, YN> P;
+    static constexpr int SMEM = P::ELEMS;
+
+    static __device__ __forceinline__ void run(const KArgs<T, OffT>& a, int64_t tile, T* smem) {
+        typedef Mfma<T> M;
+        typedef typename M::acc_t acc_t;
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int wm = wave % WM, wn = wave / WM;
+        const int64_t tm = tile % a.tiles_m, tn = tile / a.tiles_m;
+        const OffT m0 = (OffT)(tm * MT), n0 = (OffT)(tn * NT);
+
+        P pk;
+        pk.init(a, m0, n0, tid);
+        acc_t acc[FM][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[i][j][r] = T(0);
+
+        const OffT nkb = (a.k + KT - 1) / KT;
+        if (nkb > 0) {
+            pk.load(a, 0, tid);
+            pk.store(smem, 0, tid);
+            __syncthreads();
+            for (OffT kb = 0; kb < nkb; ++kb) {
+                const int buf = (int)(kb & 1);
+                const bool more = kb + 1 < nkb;
+                if (more) pk.load(a, kb + 1, tid);
+                const T* bx = smem + buf * P::XS + wm * WTM;
+                const T* by = smem + 2 * P::XS + buf * P::YS + wn * WTN;
+#pragma unroll
+                for (int s = 0; s < KT / 4; ++s) {
+                    const int kr = 4 * s + (lane >> 4);
+                    typename M::afrag fa[FM];
+                    typename M::bfrag fb[FN];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) fa[i] = M::load_a(bx + kr * P::LDX + 16 * i, lane);
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) fb[j] = M::load_b(by + kr * P::LDY + 16 * j, lane);
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) M::run(fa[i], fb[j], acc[i][j]);
+                }
+                if (more) pk.store(smem, buf ^ 1, tid);
+                __syncthreads();
+            }
+        }
+        // alpha/beta scatter-store through rscat_C / cscat_C (Sec. 6.1)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                store_frag(a, (OffT)(m0 + wm * WTM + 16 * i), (OffT)(n0 + wn * WTN + 16 * j), acc[i][j], lane);
+    }
+};
+
+// Pinwheel layout for MT = NT = 144 on four waves: the 9 x 9 grid of 16 x 16
+// fragments is covered by four rectangles of 20 fragments (4x5 at (0,0), 5x4
+// at (0,5), 4x5 at (5,4), 5x4 at (4,0)) around the centre fragment (4,4),
+// whose k-steps are dealt round-robin to the four waves and summed in LDS at
+// the end.  Every SIMD then issues exactly 20.25 fragment updates per k-step,
+// and a 2304 x 2304 output is exactly 256 tiles, one per compute unit.
+template <typename T, typename OffT, int KT, bool XM, bool YN>
+struct TilePinwheel {
+    static constexpr int MT = 144, NT = 144, NTHR = 256;
+    static_assert(KT % 16 == 0, "the centre k-split needs KT a multiple of 16");
+    typedef Pack<T, OffT, MT, NT, KT, NTHR, XM, YN> P;
+    static constexpr int SMEM = P::ELEMS > 4 * 256 ? P::ELEMS : 4 * 256;
+
+    template <int R, int C>
+    static __device__ __forceinline__ void step(typename Mfma<T>::acc_t* acc, const T* bx, const T* by, int kr, int fr0,
+                                                int fc0, int lane) {
+        typedef Mfma<T> M;
+        typename M::afrag fa[R];
+        typename M::bfrag fb[C];
+#pragma unroll
+        for (int i = 0; i < R; ++i) fa[i] = M::load_a(bx + kr * P::LDX + 16 * (fr0 + i), lane);
+#pragma unroll
+        for (int j = 0; j < C; ++j) fb[j] = M::load_b(by + kr * P::LDY + 16 * (fc0 + j), lane);
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int j = 0; j < C; ++j) M::run(fa[i], fb[j], acc[i * C + j]);
+    }
+
+    template <int R, int C>
+    static __device__ __forceinline__ void step2(typename Mfma<T>::acc_t* acc, const T* bx, const T* by, int kr, int fr0,
+                                                 int fc0, int lane, int ldx, int ldy) {
+        typedef Mfma<T> M;
+        typename M::afrag fa[R];
+        typename M::bfrag fb[C];
+#pragma unroll
+        for (int i = 0; i < R; ++i) fa[i] = M::load_a(bx + kr * ldx + 16 * (fr0 + i), lane);
+#pragma unroll
+        for (int j = 0; j < C; ++j) fb[j] = M::load_b(by + kr * ldy + 16 * (fc0 + j), lane);
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int j = 0; j < C; ++j) M::run(fa[i], fb[j], acc[i * C + j]);
+    }
+
+    template <int R, int C>
+    static __device__ __forceinline__ void epilogue(const KArgs<T, OffT>& a, const typename Mfma<T>::acc_t* acc,
+                                                    OffT m0, OffT n0, int fr0, int fc0, int lane) {
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+#pragma unroll
+            for (int j = 0; j < C; ++j)
+                store_frag(a, (OffT)(m0 + 16 * (fr0 + i)), (OffT)(n0 + 16 * (fc0 + j)), acc[i * C + j], lane);
+    }
+
+    static __device__ __forceinline__ void run(const KArgs<T, OffT>& a, int64_t tile, T* smem) {
+        typedef Mfma<T> M;
+        typedef typename M::acc_t acc_t;
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        // rectangle of this wave (in fragments)
+        const bool wide = (wave & 1) == 0;  // 4 x 5 for waves 0 and 2, 5 x 4 for 1 and 3
+        const int fr0 = wave == 2 ? 5 : wave == 3 ? 4 : 0;
+        const int fc0 = wave == 1 ? 5 : wave == 2 ? 4 : 0;
+        const int64_t tm = tile % a.tiles_m, tn = tile / a.tiles_m;
+        const OffT m0 = (OffT)(tm * MT), n0 = (OffT)(tn * NT);
+
+        P pk;
+        pk.init(a, m0, n0, tid);
+        acc_t acc[20], accc;
+#pragma unroll
+        for (int f = 0; f < 20; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[f][r] = T(0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accc[r] = T(0);
+
+        const OffT nkb = (a.k + KT - 1) / KT;
+        if (nkb > 0) {
+            pk.load(a, 0, tid);
+            pk.store(smem, 0, tid);
+            __syncthreads();
+            for (OffT kb = 0; kb < nkb; ++kb) {
+                const int buf = (int)(kb & 1);
+                const bool more = kb + 1 < nkb;
+                if (more) pk.load(a, kb + 1, tid);
+                const T* bx = smem + buf * P::XS;
+                const T* by = smem + 2 * P::XS + buf * P::YS;
+#pragma unroll
+                for (int s = 0; s < KT / 4; ++s) {
+                    const int kr = 4 * s + (lane >> 4);
+                    if (wide) step<4, 5>(acc, bx, by, kr, fr0, fc0, lane);
+                    else step<5, 4>(acc, bx, by, kr, fr0, fc0, lane);
+                    if ((s & 3) == wave)
+                        M::run(M::load_a(bx + kr * P::LDX + 64, lane), M::load_b(by + kr * P::LDY + 64, lane), accc);
+                }
+                if (more) pk.store(smem, buf ^ 1, tid);
+                __syncthreads();
+            }
+        }
+        if (wide) epilogue<4, 5>(a, acc, m0, n0, fr0, fc0, lane);
+        else epilogue<5, 4>(a, acc, m0, n0, fr0, fc0, lane);
+        // centre fragment: partial sums of the four waves added in wave order
+#pragma unroll
+        for (int r = 0; r < 4; ++r) smem[wave * 256 + r * 64 + lane] = accc[r];
+        __syncthreads();
+        if (wave == 0) {
+            acc_t v;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T x = smem[r * 64 + lane];
+                x += smem[256 + r * 64 + lane];
+                x += smem[512 + r * 64 + lane];
+                x += smem[768 + r * 64 + lane];
+                v[r] = x;
+            }
+            store_frag(a, (OffT)(m0 + 64), (OffT)(n0 + 64), v, lane);
+        }
+    }
+};
+
+// The pack stage of one operand, with the operand (and so the lane
+// direction and LDS pitch) chosen at run time: used where a wave gathers
+// either X or Y, so that only one set of gather registers is live.
+template <typename T, typename OffT, int R, int KT, int NTHR>
+struct PackRole {
+    static constexpr int E = R * KT / NTHR;
+    static_assert((R * KT) % NTHR == 0, "stage must split evenly over threads");
+    OffT o[E];  // -1 past the edge
+    T r[E];
+    bool lr;  // lanes along the free index
+    int ld;   // LDS pitch
+    __device__ __forceinline__ int ridx(int e) const { return lr ? e % R : e / KT; }
+    __device__ __forceinline__ int kidx(int e) const { return lr ? e / R : e % KT; }
+    __device__ __forceinline__ void init(const OffT* rowvec, OffT r0, OffT rmax, int t, bool lanes_row, int pitch) {
+        lr = lanes_row;
+        ld = pitch;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const OffT rr = r0 + ridx(t + NTHR * i);
+            const OffT x = rowvec[rr < rmax ? rr : rmax - 1];
+            o[i] = rr < rmax ? x : OffT(-1);
+        }
+    }
+    __device__ __forceinline__ void load(const T* base, int64_t span, const OffT* kvec, const OffT* kbs, OffT kb, OffT K,
+                                         int t) {
+        const OffT k0 = kb * KT;
+        const OffT sk = kbs[kb];
+        OffT ko[E];
+        OffT kbase = 0;
+        if (sk) {
+            kbase = kvec[k0];
+#pragma unroll
+            for (int i = 0; i < E; ++i) ko[i] = (OffT)kidx(t + NTHR * i) * sk;
+        } else {
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const OffT kg = k0 + kidx(t + NTHR * i);
+                ko[i] = kvec[kg < K ? kg : K - 1];
+            }
+        }
+        if constexpr (sizeof(OffT) == 4) {
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, span);
+            const uint32_t soff = (uint32_t)kbase * (uint32_t)sizeof(T);
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const bool ok = o[i] >= 0 && k0 + kidx(t + NTHR * i) < K;
+                const uint32_t vo = ok ? (uint32_t)(o[i] + ko[i]) * (uint32_t)sizeof(T) : kOutOfRange;
+                r[i] = buf_load<T>(rs, vo, soff);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const bool ok = o[i] >= 0 && k0 + kidx(t + NTHR * i) < K;
+                const T x = base[ok ? kbase + o[i] + ko[i] : OffT(0)];
+                r[i] = ok ? x : T(0);
+            }
+        }
+    }
+    __device__ __forceinline__ void store(T* stage, int t) const {
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const int e = t + NTHR * i;
+            stage[kidx(e) * ld + ridx(e)] = r[i];
+        }
+    }
+};
+
+// Pinwheel layout on eight waves (two per SIMD): each rectangle of the
+// four-wave pinwheel is halved (2x5 or 5x2 fragments per wave) and the centre
+// fragment's k-steps are dealt round-robin over the eight waves.  Waves 0-3
+// gather the X sliver and waves 4-7 the Y sliver of each stage.
+template <typename T, typename OffT, int KT, bool XM, bool YN>
+struct TilePinwheel8 {
+    static constexpr int MT = 144, NT = 144, NTHR = 512;
+    static_assert(KT % 4 == 0, "KT must be a multiple of the MFMA depth");
+    typedef PackRole<T, OffT, 144, KT, 256> PR;
+    static constexpr int LDX = Pitch<MT, XM>::value, LDY = Pitch<NT, YN>::value;
+    static constexpr int XS = KT * LDX, YS = KT * LDY;
+    static constexpr int ELEMS = 2 * (XS + YS);
+    static constexpr int SMEM = ELEMS > 8 * 256 ? ELEMS : 8 * 256;
+    typedef typename MfmaFor<T, true>::type MW;  // every wave runs a 2 x 5 rectangle
+
+    static __device__ __forceinline__ void run(const KArgs<T, OffT>& a, int64_t tile, T* smem) {
+        typedef Mfma<T> M;
+        typedef typename M::acc_t acc_t;
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int tt = tid & 255;  // thread index inside the gathering half
+        const int q = wave >> 1, h = wave & 1;
+        const bool wide = (q & 1) == 0;
+        const int fr0 = q == 0 ? 2 * h : q == 1 ? 0 : q == 2 ? 5 + 2 * h : 4;
+        const int fc0 = q == 0 ? 0 : q == 1 ? 5 + 2 * h : q == 2 ? 4 : 2 * h;
+        const int64_t tm = tile % a.tiles_m, tn = tile / a.tiles_m;
+        const OffT m0 = (OffT)(tm * MT), n0 = (OffT)(tn * NT);
+        const bool gx = wave < 4;
+        const int p0 = wide ? fr0 : fc0, q0 = wide ? fc0 : fr0;
+        const int ldp = wide ? LDX : LDY, ldq = wide ? LDY : LDX;
+        // this wave's operand
+        const T* gbase = gx ? a.X : a.Y;
+        const int64_t gspan = gx ? a.spanX : a.spanY;
+        const OffT* gk = gx ? a.cX : a.rY;
+        const OffT* gbs = gx ? a.kbsX : a.kbsY;
+        T* gstage = gx ? smem : smem + 2 * XS;
+        const int gsz = gx ? XS : YS;
+
+        PR pk;
+        if (gx) pk.init(a.rX, m0, a.m, tt, XM, LDX);
+        else pk.init(a.cY, n0, a.n, tt, YN, LDY);
+        acc_t acc[10], accc;
+#pragma unroll
+        for (int f = 0; f < 10; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[f][r] = T(0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) accc[r] = T(0);
+
+        const OffT nkb = (a.k + KT - 1) / KT;
+        if (nkb > 0) {
+            pk.load(gbase, gspan, gk, gbs, 0, a.k, tt);
+            pk.store(gstage, tt);
+            __syncthreads();
+            for (OffT kb = 0; kb < nkb; ++kb) {
+                const int buf = (int)(kb & 1);
+                const bool more = kb + 1 < nkb;
+                if (more) pk.load(gbase, gspan, gk, gbs, kb + 1, a.k, tt);
+                const T* bx = smem + buf * XS;
+                const T* by = smem + 2 * XS + buf * YS;
+                // a 5 x 2 rectangle of C is run as the 2 x 5 rectangle of C^T:
+                // the Y stage feeds the A side and the X stage the B side
+                const T* bp = wide ? bx : by;
+                const T* bq = wide ? by : bx;
+#pragma unroll
+                for (int s = 0; s < KT / 4; ++s) {
+                    const int kr = 4 * s + (lane >> 4);
+                    rect_step<T, MW, 2, 5>(acc, bp + kr * ldp, bq + kr * ldq, p0, q0, lane);
+                    if ((int)((kb * (KT / 4) + s) & 7) == wave)
+                        M::run(M::load_a(bx + kr * LDX + 64, lane), M::load_b(by + kr * LDY + 64, lane), accc);
+                }
+                if (more) pk.store(gstage + (buf ^ 1) * gsz, tt);
+                __syncthreads();
+            }
+        }
+        if (wide) rect_store<T, OffT, MW, 2, 5>(a, acc, m0, n0, fr0, fc0, lane);
+        else rect_store_t<T, OffT, MW, 2, 5>(a, acc, m0, n0, fc0, fr0, lane);
+        // centre fragment: partial sums of the eight waves added in wave order
+#pragma unroll
+        for (int r = 0; r < 4; ++r) smem[wave * 256 + r * 64 + lane] = accc[r];
+        __syncthreads();
+        if (wave == 0) {
+            acc_t v;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T x = smem[r * 64 + lane];
+#pragma unroll
+                for (int w = 1; w < 8; ++w) x += smem[w * 256 + r * 64 + lane];
+                v[r] = x;
+            }
+            store_frag(a, (OffT)(m0 + 64), (OffT)(n0 + 64), v, lane);
+        }
+    }
+};
+
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT, bool XM, bool YN>
+struct TileOf {
+    typedef TileRegular<T, OffT, MT, NT, KT, WM, WN, XM, YN> type;
+    static constexpr int threads = WM * WN * 64;
+};
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
+struct TileOf<T, OffT, MT, NT, KT, WM, WN, 1, XM, YN> {
+    typedef TilePinwheel<T, OffT, KT, XM, YN> type;
+    static constexpr int threads = 256;
+};
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
+struct TileOf<T, OffT, MT, NT, KT, WM, WN, 2, XM, YN> {
+    typedef TilePinwheel8<T, OffT, KT, XM, YN> type;
+    static constexpr int threads = 512;
+};
+
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT, bool XM, bool YN>
+__global__ __launch_bounds__((TileOf<T, OffT, MT, NT, KT, WM, WN, LAYOUT, XM, YN>::threads)) void contract_kernel(
+    KArgs<T, OffT> a) {
+    typedef typename TileOf<T, OffT, MT, NT, KT, WM, WN, LAYOUT, XM, YN>::type Tile;
+    __shared__ T smem[Tile::SMEM];
+    Tile::run(a, blockIdx.x, smem);
+}
+
+// C := beta * C over the matrix view (k == 0 or alpha == 0).
+template <typename T, typename OffT>
+__global__ __launch_bounds__(256) void scale_kernel(T* C, const OffT* rC, const OffT* cC, OffT m, OffT n, T beta) {
+    const int64_t total = (int64_t)m * n;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const OffT i = (OffT)(t % m), j = (OffT)(t / m);
+        const OffT o = rC[i] + cC[j];
+        C[o] = beta == T(0) ? T(0) : beta * C[o];
+    }
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return TC_ERR_HIP;
+}
+
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT>
+static int launch_tile(const KArgs<T, OffT>& a, bool xm, bool yn, hipStream_t s) {
+    const int64_t tiles = a.tiles_m * a.tiles_n;
+    if (tiles <= 0) return TC_OK;
+    if (tiles > 0x7fffffffLL) {
+        set_error("too many tiles for one launch");
+        return TC_ERR_ARG;
+    }
+    dim3 grid((unsigned)tiles), block(TileOf<T, OffT, MT, NT, KT, WM, WN, LAYOUT, true, true>::threads);
+    if (xm && yn)
+        hipLaunchKernelGGL((contract_kernel<T, OffT, MT, NT, KT, WM, WN, LAYOUT, true, true>), grid, block, 0, s, a);
+    else if (xm)
+        hipLaunchKernelGGL((contract_kernel<T, OffT, MT, NT, KT, WM, WN, LAYOUT, true, false>), grid, block, 0, s, a);
+    else if (yn)
+        hipLaunchKernelGGL((contract_kernel<T, OffT, MT, NT, KT, WM, WN, LAYOUT, false, true>), grid, block, 0, s, a);
+    else
+        hipLaunchKernelGGL((contract_kernel<T, OffT, MT, NT, KT, WM, WN, LAYOUT, false, false>), grid, block, 0, s, a);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TC_OK : hip_fail(e, "kernel launch");
+}
+
+template <typename T, typename OffT>
+static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B,
+                        double beta, void* C, hipStream_t s) {
+    const OffT* base = (const OffT*)dv.buf;
+    KArgs<T, OffT> a;
+    a.X = (const T*)(p.swapped ? B : A);
+    a.Y = (const T*)(p.swapped ? A : B);
+    a.C = (T*)C;
+    a.rX = base + dv.o_rX;
+    a.cX = base + dv.o_cX;
+    a.rY = base + dv.o_rY;
+    a.cY = base + dv.o_cY;
+    a.rC = base + dv.o_rC;
+    a.cC = base + dv.o_cC;
+    a.kbsX = base + dv.o_kbsX;
+    a.kbsY = base + dv.o_kbsY;
+    a.m = (OffT)p.m;
+    a.n = (OffT)p.n;
+    a.k = (OffT)p.k;
+    a.tiles_m = p.tiles_m;
+    a.tiles_n = p.tiles_n;
+    a.spanX = p.swapped ? p.spanB : p.spanA;
+    a.spanY = p.swapped ? p.spanA : p.spanB;
+    a.alpha = (T)alpha;
+    a.beta = (T)beta;
+    if (p.m == 0 || p.n == 0) return TC_OK;
+    if (p.k_empty || p.k == 0 || alpha == 0.0) {
+        int64_t total = p.m * p.n;
+        int64_t blocks = (total + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL((scale_kernel<T, OffT>), dim3((unsigned)blocks), dim3(256), 0, s, (T*)C, a.rC, a.cC, a.m,
+                           a.n, (T)beta);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? TC_OK : hip_fail(e, "kernel launch");
+    }
+    const bool xm = p.x_lanes_m, yn = p.y_lanes_n;
+#define TC_CASE(id, MT, NT, KT, WM, WN, L) \
+    case id:                               \
+        return launch_tile<T, OffT, MT, NT, KT, WM, WN, L>(a, xm, yn, s);
+    if (p.dtype == TC_F64) {
+        switch (p.tile) { TC_TILES_F64(TC_CASE) }
+    } else {
+        switch (p.tile) { TC_TILES_F32(TC_CASE) }
+    }
+#undef TC_CASE
+    set_error("unknown tile configuration");
+    return TC_ERR_ARG;
+}
+
+// Persistent batched kernel: workgroup g processes work items g, g + G, ...
+// of a flattened (problem, tile) list; problems are ordered by decreasing
+// cost per tile, so the static stride assignment stays balanced.  Every
+// problem may have its own lane directions, so the four pack variants are
+// dispatched per item.
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN>
+__global__ __launch_bounds__(WM* WN * 64) void batch_kernel(const BatchItemDev* __restrict__ items, int count,
+                                                           int64_t total) {
+    typedef TileRegular<T, OffT, MT, NT, KT, WM, WN, true, true> TTT;
+    typedef TileRegular<T, OffT, MT, NT, KT, WM, WN, true, false> TTF;
+    typedef TileRegular<T, OffT, MT, NT, KT, WM, WN, false, true> TFT;
+    typedef TileRegular<T, OffT, MT, NT, KT, WM, WN, false, false> TFF;
+    constexpr int S1 = TTT::SMEM > TTF::SMEM ? TTT::SMEM : TTF::SMEM;
+    constexpr int S2 = TFT::SMEM > TFF::SMEM ? TFT::SMEM : TFF::SMEM;
+    __shared__ T smem[S1 > S2 ? S1 : S2];
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].first_item <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchItemDev& it = items[lo];
+        KArgs<T, OffT> a;
+        a.X = (const T*)it.X;
+        a.Y = (const T*)it.Y;
+        a.C = (T*)it.C;
+        a.rX = (const OffT*)it.rX;
+        a.cX = (const OffT*)it.cX;
+        a.rY = (const OffT*)it.rY;
+        a.cY = (const OffT*)it.cY;
+        a.rC = (const OffT*)it.rC;
+        a.cC = (const OffT*)it.cC;
+        a.kbsX = (const OffT*)it.kbsX;
+        a.kbsY = (const OffT*)it.kbsY;
+        a.m = (OffT)it.m;
+        a.n = (OffT)it.n;
+        a.k = (OffT)it.k;
+        a.tiles_m = it.tiles_m;
+        a.tiles_n = it.tiles_n;
+        a.spanX = it.spanX;
+        a.spanY = it.spanY;
+        a.alpha = (T)it.alpha;
+        a.beta = (T)it.beta;
+        const int64_t tile = w - it.first_item;
+        if (it.x_lanes_m) {
+            if (it.y_lanes_n) TTT::run(a, tile, smem);
+            else TTF::run(a, tile, smem);
+        } else {
+            if (it.y_lanes_n) TFT::run(a, tile, smem);
+            else TFF::run(a, tile, smem);
+        }
+        __syncthreads();  // LDS is reused by the next item
+    }
+}
+
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int L>
+struct BatchLaunch {
+    static int launch(const BatchItemDev* items, int count, int64_t total, int grid, hipStream_t s) {
+        if constexpr (L != 0) {
+            set_error("batched launches use the regular tile layouts");
+            return TC_ERR_ARG;
+        } else {
+            hipLaunchKernelGGL((batch_kernel<T, OffT, MT, NT, KT, WM, WN>), dim3(grid), dim3(WM * WN * 64), 0, s,
+                               items, count, total);
+            hipError_t e = hipGetLastError();
+            return e == hipSuccess ? TC_OK : hip_fail(e, "batched kernel launch");
+        }
+    }
+    static int grid(int64_t total) {
+        if constexpr (L != 0) {
+            return 0;
+        } else {
+            int dev = 0, cus = 0, per_cu = 0;
+            if (hipGetDevice(&dev) != hipSuccess) return 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, (const void*)batch_kernel<T, OffT, MT, NT, KT, WM, WN>, WM * WN * 64, 0) != hipSuccess)
+                return 0;
+            int64_t g = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+            return (int)(total < g ? total : g);
+        }
+    }
+};
+
+template <typename T, typename OffT>
+static int batch_dispatch(int dtype, int tile, bool launch, const BatchItemDev* items, int count, int64_t total,
+                          int grid, hipStream_t s) {
+#define TC_BCASE(id, MT, NT, KT, WM, WN, L)                                                               \
+    case id:                                                                                              \
+        return launch ? BatchLaunch<T, OffT, MT, NT, KT, WM, WN, L>::launch(items, count, total, grid, s) \
+                      : BatchLaunch<T, OffT, MT, NT, KT, WM, WN, L>::grid(total);
+    if (dtype == TC_F64) {
+        switch (tile) { TC_TILES_F64(TC_BCASE) }
+    } else {
+        switch (tile) { TC_TILES_F32(TC_BCASE) }
+    }
+#undef TC_BCASE
+    set_error("unknown tile configuration");
+    return launch ? TC_ERR_ARG : 0;
+}
+
+}  // namespace tc

@@ -12,12 +12,13 @@ namespace tc {
 int launch_plan(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
                 void* C, hipStream_t stream);
 
-// One problem of a batched launch, as seen by the device.
+// One problem of a batched launch, as seen by the device.  Offset vectors
+// are int32 or int64 for the whole batch.
 struct BatchItemDev {
     const void* X;
     const void* Y;
     void* C;
-    const void* rX;  // offset vectors (int32 or int64, see off64 of the batch)
+    const void* rX;
     const void* cX;
     const void* rY;
     const void* cY;
@@ -25,19 +26,21 @@ struct BatchItemDev {
     const void* cC;
     const void* kbsX;
     const void* kbsY;
-    int64_t m, n, k;
+    int64_t m, n, k;  // k = 0 when only C := beta C is needed
     int64_t tiles_m, tiles_n;
-    int64_t first_item;  // prefix sum of tile counts
+    int64_t first_item;  // index of this problem's first work item
+    int64_t spanX, spanY;
     double alpha, beta;
-    int x_lanes_m, y_lanes_n;
-    int scale_only;  // k == 0 or alpha == 0: C := beta C
-    int pad_;
+    int32_t x_lanes_m, y_lanes_n;
 };
 
-// Launch the persistent batched kernel over `count` items (table on device).
+// Launch the persistent batched kernel of tile configuration `tile` over
+// `count` problems (table on the device, ordered by first_item) covering
+// total_items work items, with `grid` workgroups.
 int launch_batch(int dtype, int mode, int tile, bool off64, const BatchItemDev* items_dev, int count,
                  int64_t total_items, int grid, hipStream_t stream);
-// Persistent grid size for a batched launch of the given tile.
-int batch_grid(int dtype, int mode, int tile, int64_t total_items);
+// Workgroups of a persistent batched launch: min(total_items, resident
+// workgroups of the tile's kernel on the current device).
+int batch_grid(int dtype, int mode, int tile, bool off64, int64_t total_items);
 
 }  // namespace tc

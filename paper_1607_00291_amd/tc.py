@@ -21,6 +21,7 @@ EXPORTS = [
     "tc_contract", "tc_plan_create", "tc_plan_upload", "tc_plan_execute", "tc_plan_destroy",
     "tc_plan_describe", "tc_tile_count", "tc_tile_info", "tc_plan_set_tile", "tc_plan_get_tile",
     "tc_plan_autotune", "tc_batch_create", "tc_batch_execute", "tc_batch_destroy", "tc_batch_info",
+    "tc_batch_set_tile", "tc_batch_autotune",
     "tc_scatter_vector", "tc_block_strides", "tc_status_string", "tc_last_error",
 ]
 
@@ -63,6 +64,8 @@ def lib():
         L.tc_batch_execute.argtypes = [_vp, _vp]
         L.tc_batch_destroy.argtypes = [_vp]
         L.tc_batch_info.argtypes = [_vp, _i64p, ip, ip]
+        L.tc_batch_set_tile.argtypes = [_vp, ctypes.c_int]
+        L.tc_batch_autotune.argtypes = [_vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double)]
         L.tc_scatter_vector.argtypes = [ctypes.c_int, _i64p, _i64p, _i64p]
         L.tc_block_strides.argtypes = [_i64p, ctypes.c_int64, ctypes.c_int64, _i64p]
         L.tc_status_string.argtypes = [ctypes.c_int]
@@ -195,6 +198,64 @@ class Plan:
         if self._h:
             lib().tc_plan_destroy(self._h)
             self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent contractions run by one persistent kernel launch.
+
+    ``problems`` is a list of (A, idx_A, B, idx_B, C, idx_C, alpha, beta) with
+    torch tensors on the current device, all of one dtype.  The tensors are
+    bound at construction (their pointers go into the device work table), so
+    they must stay alive while the batch is used.  ``execute`` issues a single
+    kernel launch and may be recorded in a CUDA/HIP graph.
+    """
+
+    def __init__(self, problems, mode="native"):
+        self._h = _vp()
+        self.plans = [Plan.for_tensors(A, ia, B, ib, C, ic, mode=mode) for (A, ia, B, ib, C, ic, _, _) in problems]
+        n = len(problems)
+        self.tensors = [(p[0], p[2], p[4]) for p in problems]  # keep alive
+        hs = (_vp * max(n, 1))(*[p.handle for p in self.plans])
+        al = (ctypes.c_double * max(n, 1))(*[float(p[6]) for p in problems])
+        be = (ctypes.c_double * max(n, 1))(*[float(p[7]) for p in problems])
+        As = (_vp * max(n, 1))(*[_ptr(p[0]) for p in problems])
+        Bs = (_vp * max(n, 1))(*[_ptr(p[2]) for p in problems])
+        Cs = (_vp * max(n, 1))(*[_ptr(p[4]) for p in problems])
+        _check(lib().tc_batch_create(ctypes.byref(self._h), n, hs, al, As, Bs, be, Cs))
+
+    def execute(self, stream=None):
+        _check(lib().tc_batch_execute(self._h, _stream_ptr(stream)))
+
+    def info(self):
+        w, t, g = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().tc_batch_info(self._h, ctypes.byref(w), ctypes.byref(t), ctypes.byref(g)))
+        return {"work_items": w.value, "tile": t.value, "grid": g.value}
+
+    @property
+    def tile(self):
+        return self.info()["tile"]
+
+    @tile.setter
+    def tile(self, t):
+        _check(lib().tc_batch_set_tile(self._h, int(t)))
+
+    def autotune(self, reps=3, stream=None):
+        best = ctypes.c_double()
+        _check(lib().tc_batch_autotune(self._h, int(reps), _stream_ptr(stream), ctypes.byref(best)))
+        return self.tile, best.value
+
+    def close(self):
+        if self._h:
+            lib().tc_batch_destroy(self._h)
+            self._h = _vp()
+        for p in getattr(self, "plans", []):
+            p.close()
 
     def __del__(self):
         try:

@@ -1,0 +1,113 @@
+"""Batched contractions in one persistent launch: bitwise equality with
+sequential launches of the same tile configuration, parity with the oracle,
+and graph capture with several replays."""
+import numpy as np
+import pytest
+
+from paper_1607_00291_amd import inputs
+from gpuutil import fp64_bound, require_gpu, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def subset(n):
+    """The n cheapest instances of the 512-problem workload, plus 4 large ones."""
+    probs = [inputs.cfg5_instance(i) for i in range(64)]
+    probs.sort(key=lambda p: p.flops())
+    return probs[:n] + probs[-4:]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_batched_equals_sequential_and_oracle(oracle_mod, dtype):
+    torch = require_gpu()
+    from paper_1607_00291_amd import tc
+    probs = subset(24)
+    dev = [(to_dev(p.A, dtype), to_dev(p.B, dtype), to_dev(p.C, dtype)) for p in probs]
+    seq_out = [to_dev(p.C, dtype) for p in probs]
+    batch = tc.Batch([(A, p.idx_A, B, p.idx_B, C, p.idx_C, p.alpha, p.beta) for p, (A, B, C) in zip(probs, dev)])
+    info = batch.info()
+    print(f"case batched dtype={dtype.__name__} {info}", flush=True)
+    batch.execute()
+    # sequential launches with the batch's tile configuration
+    for p, (A, B, _), Cs in zip(probs, dev, seq_out):
+        plan = tc.Plan.for_tensors(A, p.idx_A, B, p.idx_B, Cs, p.idx_C)
+        plan.tile = info["tile"]
+        plan.execute(A, B, Cs, p.alpha, p.beta)
+        plan.close()
+    torch.cuda.synchronize()
+    for p, (_, _, C), Cs in zip(probs, dev, seq_out):
+        assert np.array_equal(to_host(C), to_host(Cs)), p.name
+    if dtype == np.float64:
+        for p, (_, _, C) in zip(probs[:8] + probs[-2:], dev[:8] + dev[-2:]):
+            ref = np.array(p.C, order="F", copy=True)
+            oracle_mod.contract(p.alpha, p.A, p.idx_A, p.B, p.idx_B, p.beta, ref, p.idx_C)
+            bound = fp64_bound(p.mnk()[2], p.alpha, np.max(np.abs(p.A)), np.max(np.abs(p.B)))
+            assert np.max(np.abs(to_host(C) - ref)) <= bound, p.name
+    batch.close()
+
+
+def test_batched_every_tile_and_graph_replay(oracle_mod):
+    torch = require_gpu()
+    from paper_1607_00291_amd import tc
+    probs = subset(12)
+    dev = [(to_dev(p.A), to_dev(p.B), to_dev(p.C)) for p in probs]
+    batch = tc.Batch([(A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 0.0) for p, (A, B, C) in zip(probs, dev)])
+    ref = None
+    for t in range(tc.tile_count(tc.TC_F64)):
+        MT, NT, KT, waves = tc.tile_info(tc.TC_F64, tc.TC_NATIVE, t)
+        if MT == 144:  # pinwheel layouts are single-problem only
+            continue
+        batch.tile = t
+        for _, _, C in dev:
+            C.zero_()
+        batch.execute()
+        torch.cuda.synchronize()
+        outs = [to_host(C) for _, _, C in dev]
+        print(f"case batched tile={t}", flush=True)
+        if ref is None:
+            ref = outs
+        else:  # every regular tile sums in the same order: bitwise equal
+            for a, b in zip(ref, outs):
+                assert np.array_equal(a, b)
+    # graph capture of the single persistent launch, replayed with eager work
+    # in between; every replay must reproduce the eager result
+    batch.tile = 1
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.execute(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.execute()
+    for rep in range(3):
+        for _, _, C in dev:
+            C.fill_(float(rep + 7))  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, (_, _, C) in zip(ref, dev):
+            assert np.array_equal(a, to_host(C)), f"replay {rep}"
+    batch.close()
+
+
+def test_autotune_batch_and_plan():
+    torch = require_gpu()
+    from paper_1607_00291_amd import tc
+    probs = subset(6)
+    dev = [(to_dev(p.A), to_dev(p.B), to_dev(p.C)) for p in probs]
+    batch = tc.Batch([(A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 0.0) for p, (A, B, C) in zip(probs, dev)])
+    tile, ms = batch.autotune(reps=2)
+    assert ms > 0 and 0 <= tile < tc.tile_count(tc.TC_F64)
+    p = probs[-1]
+    A, B, C = dev[-1]
+    plan = tc.Plan.for_tensors(A, p.idx_A, B, p.idx_B, C, p.idx_C)
+    tile, ms = plan.autotune(A, B, C, reps=2)
+    assert ms > 0
+    # a new plan with the same signature starts from the tuned tile
+    plan2 = tc.Plan.for_tensors(A, p.idx_A, B, p.idx_B, C, p.idx_C)
+    assert plan2.tile == tile
+    plan.close()
+    plan2.close()
+    batch.close()
