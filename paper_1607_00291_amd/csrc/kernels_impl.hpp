@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <cstdio>
 
 #include "launch.hpp"
@@ -163,6 +164,16 @@ struct Pitch {
     static constexpr int value = LANES_ALONG_ROW ? W : W + 1;
 };
 
+// Values every lane of a wave holds equally (loaded from a uniform address),
+// moved to scalar registers so that they can serve as a buffer load's scalar
+// offset and as branch conditions without per-lane handling.
+__device__ __forceinline__ int32_t uniform(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uniform(int64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint64_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Bounds-checked buffer loads (32-bit-offset plans): a byte offset at or past
 // the buffer's size reads 0, so ragged edges need no select after the load
 // and every load of a stage can stay in flight until the LDS write.
@@ -216,11 +227,11 @@ struct PackOp {
     __device__ __forceinline__ void load(const T* base, int64_t span, const OffT* kvec, const OffT* kbs, OffT kb, OffT K,
                                          int t) {
         const OffT k0 = kb * KT;
-        const OffT sk = kbs[kb];
+        const OffT sk = uniform(kbs[kb]);
         OffT ko[E];
         OffT kbase = 0;
         if (sk) {
-            kbase = kvec[k0];
+            kbase = uniform(kvec[k0]);
 #pragma unroll
             for (int i = 0; i < E; ++i) ko[i] = (OffT)kidx(t + NTHR * i) * sk;
         } else {
@@ -232,7 +243,7 @@ struct PackOp {
         }
         if constexpr (sizeof(OffT) == 4) {
             const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, span);
-            const uint32_t soff = (uint32_t)kbase * (uint32_t)sizeof(T);
+            const uint32_t soff = (uint32_t)uniform((int32_t)((uint32_t)kbase * (uint32_t)sizeof(T)));
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 const bool ok = o[i] >= 0 && k0 + kidx(t + NTHR * i) < K;
@@ -312,6 +323,24 @@ __device__ __forceinline__ void rect_step(typename M::acc_t* acc, const T* bx, c
     for (int i = 0; i < R; ++i) fa[i] = M::load_a(bx + 16 * (fr0 + i), lane);
 #pragma unroll
     for (int j = 0; j < C; ++j) fb[j] = M::load_b(by + 16 * (fc0 + j), lane);
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < C; ++j) M::run(fa[i], fb[j], acc[i * C + j]);
+}
+
+template <typename T, typename M, int R, int C>
+__device__ __forceinline__ void rect_load(typename M::afrag* fa, typename M::bfrag* fb, const T* bx, const T* by,
+                                          int fr0, int fc0, int lane) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) fa[i] = M::load_a(bx + 16 * (fr0 + i), lane);
+#pragma unroll
+    for (int j = 0; j < C; ++j) fb[j] = M::load_b(by + 16 * (fc0 + j), lane);
+}
+
+template <typename T, typename M, int R, int C>
+__device__ __forceinline__ void rect_mma(typename M::acc_t* acc, const typename M::afrag* fa,
+                                         const typename M::bfrag* fb) {
 #pragma unroll
     for (int i = 0; i < R; ++i)
 #pragma unroll
@@ -535,12 +564,12 @@ struct TilePinwheel {
 // The pack stage of one operand, with the operand (and so the lane
 // direction and LDS pitch) chosen at run time: used where a wave gathers
 // either X or Y, so that only one set of gather registers is live.
-template <typename T, typename OffT, int R, int KT, int NTHR>
+template <typename T, typename OffT, int R, int KT, int NTHR, int SLOTS = 1>
 struct PackRole {
     static constexpr int E = R * KT / NTHR;
     static_assert((R * KT) % NTHR == 0, "stage must split evenly over threads");
     OffT o[E];  // -1 past the edge
-    T r[E];
+    T r[SLOTS][E];  // stages in flight
     bool lr;  // lanes along the free index
     int ld;   // LDS pitch
     __device__ __forceinline__ int ridx(int e) const { return lr ? e % R : e / KT; }
@@ -555,14 +584,15 @@ struct PackRole {
             o[i] = rr < rmax ? x : OffT(-1);
         }
     }
+    template <int SL = 0>
     __device__ __forceinline__ void load(const T* base, int64_t span, const OffT* kvec, const OffT* kbs, OffT kb, OffT K,
                                          int t) {
         const OffT k0 = kb * KT;
-        const OffT sk = kbs[kb];
+        const OffT sk = uniform(kbs[kb]);
         OffT ko[E];
         OffT kbase = 0;
         if (sk) {
-            kbase = kvec[k0];
+            kbase = uniform(kvec[k0]);
 #pragma unroll
             for (int i = 0; i < E; ++i) ko[i] = (OffT)kidx(t + NTHR * i) * sk;
         } else {
@@ -574,27 +604,28 @@ struct PackRole {
         }
         if constexpr (sizeof(OffT) == 4) {
             const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, span);
-            const uint32_t soff = (uint32_t)kbase * (uint32_t)sizeof(T);
+            const uint32_t soff = (uint32_t)uniform((int32_t)((uint32_t)kbase * (uint32_t)sizeof(T)));
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 const bool ok = o[i] >= 0 && k0 + kidx(t + NTHR * i) < K;
                 const uint32_t vo = ok ? (uint32_t)(o[i] + ko[i]) * (uint32_t)sizeof(T) : kOutOfRange;
-                r[i] = buf_load<T>(rs, vo, soff);
+                r[SL][i] = buf_load<T>(rs, vo, soff);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 const bool ok = o[i] >= 0 && k0 + kidx(t + NTHR * i) < K;
                 const T x = base[ok ? kbase + o[i] + ko[i] : OffT(0)];
-                r[i] = ok ? x : T(0);
+                r[SL][i] = ok ? x : T(0);
             }
         }
     }
+    template <int SL = 0>
     __device__ __forceinline__ void store(T* stage, int t) const {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int e = t + NTHR * i;
-            stage[kidx(e) * ld + ridx(e)] = r[i];
+            stage[kidx(e) * ld + ridx(e)] = r[SL][i];
         }
     }
 };
@@ -607,7 +638,7 @@ template <typename T, typename OffT, int KT, bool XM, bool YN>
 struct TilePinwheel8 {
     static constexpr int MT = 144, NT = 144, NTHR = 512;
     static_assert(KT % 4 == 0, "KT must be a multiple of the MFMA depth");
-    typedef PackRole<T, OffT, 144, KT, 256> PR;
+    typedef PackRole<T, OffT, 144, KT, 256, 2> PR;
     static constexpr int LDX = Pitch<MT, XM>::value, LDY = Pitch<NT, YN>::value;
     static constexpr int XS = KT * LDX, YS = KT * LDY;
     static constexpr int ELEMS = 2 * (XS + YS);
@@ -649,29 +680,46 @@ struct TilePinwheel8 {
         for (int r = 0; r < 4; ++r) accc[r] = T(0);
 
         const OffT nkb = (a.k + KT - 1) / KT;
-        if (nkb > 0) {
-            pk.load(gbase, gspan, gk, gbs, 0, a.k, tt);
-            pk.store(gstage, tt);
-            __syncthreads();
-            for (OffT kb = 0; kb < nkb; ++kb) {
-                const int buf = (int)(kb & 1);
-                const bool more = kb + 1 < nkb;
-                if (more) pk.load(gbase, gspan, gk, gbs, kb + 1, a.k, tt);
-                const T* bx = smem + buf * XS;
-                const T* by = smem + 2 * XS + buf * YS;
-                // a 5 x 2 rectangle of C is run as the 2 x 5 rectangle of C^T:
-                // the Y stage feeds the A side and the X stage the B side
-                const T* bp = wide ? bx : by;
-                const T* bq = wide ? by : bx;
+        // Three-stage pipeline: while the matrix cores consume LDS stage kb,
+        // the gathers of stage kb + 2 are in flight in one register slot and
+        // stage kb + 1 (gathered one iteration earlier) goes from the other
+        // slot to LDS, so each gather has two stages of compute to land.
+        auto body = [&](OffT kb, auto slot) {
+            constexpr int SL = decltype(slot)::value;
+            const int buf = (int)(kb & 1);
+            if (kb + 2 < nkb) pk.template load<SL>(gbase, gspan, gk, gbs, kb + 2, a.k, tt);
+            const T* bx = smem + buf * XS;
+            const T* by = smem + 2 * XS + buf * YS;
+            // a 5 x 2 rectangle of C is run as the 2 x 5 rectangle of C^T:
+            // the Y stage feeds the A side and the X stage the B side
+            const T* bp = wide ? bx : by;
+            const T* bq = wide ? by : bx;
+            typename M::afrag ca;
+            typename M::bfrag cb;
+            const int kr0 = lane >> 4;
+            // the centre fragment's k-steps go round-robin over the waves
+            const int cs = (wave - (int)((kb * (KT / 4)) & 7)) & 7;  // this wave's centre k-step, if < KT/4
+            if (cs < KT / 4) {
+                ca = M::load_a(bx + (4 * cs + kr0) * LDX + 64, lane);
+                cb = M::load_b(by + (4 * cs + kr0) * LDY + 64, lane);
+            }
 #pragma unroll
-                for (int s = 0; s < KT / 4; ++s) {
-                    const int kr = 4 * s + (lane >> 4);
-                    rect_step<T, MW, 2, 5>(acc, bp + kr * ldp, bq + kr * ldq, p0, q0, lane);
-                    if ((int)((kb * (KT / 4) + s) & 7) == wave)
-                        M::run(M::load_a(bx + kr * LDX + 64, lane), M::load_b(by + kr * LDY + 64, lane), accc);
-                }
-                if (more) pk.store(gstage + (buf ^ 1) * gsz, tt);
-                __syncthreads();
+            for (int s = 0; s < KT / 4; ++s) {
+                const int kr = 4 * s + kr0;
+                rect_step<T, MW, 2, 5>(acc, bp + kr * ldp, bq + kr * ldq, p0, q0, lane);
+                if (cs == s) M::run(ca, cb, accc);
+            }
+            if (kb + 1 < nkb) pk.template store<1 - SL>(gstage + (buf ^ 1) * gsz, tt);
+            __syncthreads();
+        };
+        if (nkb > 0) {
+            pk.template load<0>(gbase, gspan, gk, gbs, 0, a.k, tt);
+            pk.template store<0>(gstage, tt);
+            if (nkb > 1) pk.template load<1>(gbase, gspan, gk, gbs, 1, a.k, tt);
+            __syncthreads();
+            for (OffT kb = 0; kb < nkb; kb += 2) {
+                body(kb, std::integral_constant<int, 0>());
+                if (kb + 1 < nkb) body(kb + 1, std::integral_constant<int, 1>());
             }
         }
         if (wide) rect_store<T, OffT, MW, 2, 5>(a, acc, m0, n0, fr0, fc0, lane);
