@@ -28,8 +28,8 @@ int batch_dispatch_f32_i64(int dtype, int tile, bool launch, const BatchItemDev*
 
 int launch_plan(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
                 void* C, hipStream_t s) {
-    if (p.mode != TC_NATIVE) {
-        set_error("split-bf16 mode is not built into this library");
+    if (p.mode != TC_NATIVE && !(p.mode == TC_SPLIT_BF16X3 && p.dtype == TC_F32)) {
+        set_error("split-bf16 mode needs FP32 storage");
         return TC_ERR_DTYPE;
     }
     if (p.dtype == TC_F64)

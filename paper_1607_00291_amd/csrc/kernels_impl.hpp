@@ -33,6 +33,11 @@
 
 namespace tc {
 
+static int hip_fail(hipError_t e, const char* what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return TC_ERR_HIP;
+}
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Four FP64 accumulators kept as independent scalars, so every matrix-core
@@ -638,7 +643,10 @@ template <typename T, typename OffT, int KT, bool XM, bool YN>
 struct TilePinwheel8 {
     static constexpr int MT = 144, NT = 144, NTHR = 512;
     static_assert(KT % 4 == 0, "KT must be a multiple of the MFMA depth");
-    typedef PackRole<T, OffT, 144, KT, 256, 2> PR;
+    // gather register slots: two (a three-stage pipeline) when one stage's
+    // share is small, else one (two stages: gathers of kb + 1 in flight)
+    static constexpr int SLOTS = (144 * KT / 256) * (int)sizeof(T) <= 72 ? 2 : 1;
+    typedef PackRole<T, OffT, 144, KT, 256, SLOTS> PR;
     static constexpr int LDX = Pitch<MT, XM>::value, LDY = Pitch<NT, YN>::value;
     static constexpr int XS = KT * LDX, YS = KT * LDY;
     static constexpr int ELEMS = 2 * (XS + YS);
@@ -686,8 +694,9 @@ struct TilePinwheel8 {
         // slot to LDS, so each gather has two stages of compute to land.
         auto body = [&](OffT kb, auto slot) {
             constexpr int SL = decltype(slot)::value;
+            constexpr int AHEAD = SLOTS;  // stages between a gather and its use
             const int buf = (int)(kb & 1);
-            if (kb + 2 < nkb) pk.template load<SL>(gbase, gspan, gk, gbs, kb + 2, a.k, tt);
+            if (kb + AHEAD < nkb) pk.template load<SL>(gbase, gspan, gk, gbs, kb + AHEAD, a.k, tt);
             const T* bx = smem + buf * XS;
             const T* by = smem + 2 * XS + buf * YS;
             // a 5 x 2 rectangle of C is run as the 2 x 5 rectangle of C^T:
@@ -709,17 +718,23 @@ struct TilePinwheel8 {
                 rect_step<T, MW, 2, 5>(acc, bp + kr * ldp, bq + kr * ldq, p0, q0, lane);
                 if (cs == s) M::run(ca, cb, accc);
             }
-            if (kb + 1 < nkb) pk.template store<1 - SL>(gstage + (buf ^ 1) * gsz, tt);
+            if (kb + 1 < nkb) pk.template store<(SL + 1) % SLOTS>(gstage + (buf ^ 1) * gsz, tt);
             __syncthreads();
         };
         if (nkb > 0) {
             pk.template load<0>(gbase, gspan, gk, gbs, 0, a.k, tt);
             pk.template store<0>(gstage, tt);
-            if (nkb > 1) pk.template load<1>(gbase, gspan, gk, gbs, 1, a.k, tt);
+            if constexpr (SLOTS == 2) {
+                if (nkb > 1) pk.template load<1>(gbase, gspan, gk, gbs, 1, a.k, tt);
+            }
             __syncthreads();
-            for (OffT kb = 0; kb < nkb; kb += 2) {
-                body(kb, std::integral_constant<int, 0>());
-                if (kb + 1 < nkb) body(kb + 1, std::integral_constant<int, 1>());
+            if constexpr (SLOTS == 2) {
+                for (OffT kb = 0; kb < nkb; kb += 2) {
+                    body(kb, std::integral_constant<int, 0>());
+                    if (kb + 1 < nkb) body(kb + 1, std::integral_constant<int, 1>());
+                }
+            } else {
+                for (OffT kb = 0; kb < nkb; ++kb) body(kb, std::integral_constant<int, 0>());
             }
         }
         if (wide) rect_store<T, OffT, MW, 2, 5>(a, acc, m0, n0, fr0, fc0, lane);
@@ -741,6 +756,231 @@ struct TilePinwheel8 {
         }
     }
 };
+
+// ---------------------------------------------------------------------------
+// Split-BF16 mode (FP32 storage): every FP32 operand element x is split at
+// pack time into hi = rn_bf16(x) and lo = rn_bf16(x - hi), and each 16x16
+// fragment update over depth 32 is three bf16 matrix-core products
+// lo*hi + hi*lo + hi*hi (the small terms first) accumulated in FP32.  The
+// lo*lo term and the residual of the split (|x - hi - lo| <= 2^-16 |x|) are
+// dropped, so the result carries a relative error of about 3 * 2^-16 per
+// product plus FP32 accumulation; FP64 stays the path for ill-conditioned
+// inputs.
+// ---------------------------------------------------------------------------
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// round-to-nearest-even FP32 -> bf16 bits; NaN stays NaN
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, x);
+    if (x != x) return 0x7fc0u;
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_value(uint32_t h) { return __builtin_bit_cast(float, h << 16); }
+
+// hi and lo halves of x (lo = 0 when x is not finite)
+__device__ __forceinline__ void split_bf16(float x, uint32_t& hi, uint32_t& lo) {
+    hi = bf16_bits(x);
+    const float r = x - bf16_value(hi);
+    lo = (r == r && __builtin_fabsf(r) != __builtin_inff()) ? bf16_bits(r) : 0u;
+}
+
+// Pack stage of one operand for the split mode: each thread gathers pairs of
+// consecutive k of one row (the pair is one 32-bit LDS word per plane).
+// Planes are row-major [R][KTP] bf16 (k contiguous), the order in which the
+// bf16 matrix-core operands read 8 consecutive k per lane.
+template <typename OffT, int R, int KT, int NTHR, bool LR>
+struct PackPair {
+    static constexpr int KP = KT / 2;
+    static constexpr int EP = R * KP / NTHR;  // pairs per thread
+    static constexpr int KTP = KT + 8;        // plane pitch in bf16 (16-byte multiple, spreads the banks)
+    static constexpr int PLANE = R * KTP;     // bf16 elements of one plane
+    static_assert((R * KP) % NTHR == 0, "stage must split evenly over threads");
+    static __device__ __forceinline__ int ridx(int q) { return LR ? q % R : q / KP; }
+    static __device__ __forceinline__ int pidx(int q) { return LR ? q / R : q % KP; }
+    OffT o[EP];
+    float r0[EP], r1[EP];
+    __device__ __forceinline__ void init(const OffT* rowvec, OffT r0_, OffT rmax, int t) {
+#pragma unroll
+        for (int i = 0; i < EP; ++i) {
+            const OffT rr = r0_ + ridx(t + NTHR * i);
+            const OffT x = rowvec[rr < rmax ? rr : rmax - 1];
+            o[i] = rr < rmax ? x : OffT(-1);
+        }
+    }
+    __device__ __forceinline__ void load(const float* base, int64_t span, const OffT* kvec, const OffT* kbs, OffT kb,
+                                         OffT K, int t) {
+        const OffT k0 = kb * KT;
+        const OffT sk = uniform(kbs[kb]);
+        OffT kbase = 0;
+        OffT ko0[EP], ko1[EP];
+        if (sk) {
+            kbase = uniform(kvec[k0]);
+#pragma unroll
+            for (int i = 0; i < EP; ++i) {
+                const OffT kk = 2 * pidx(t + NTHR * i);
+                ko0[i] = kk * sk;
+                ko1[i] = (kk + 1) * sk;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < EP; ++i) {
+                const OffT kg = k0 + 2 * pidx(t + NTHR * i);
+                ko0[i] = kvec[kg < K ? kg : K - 1];
+                ko1[i] = kvec[kg + 1 < K ? kg + 1 : K - 1];
+            }
+        }
+        if constexpr (sizeof(OffT) == 4) {
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, span);
+            const uint32_t soff = (uint32_t)uniform((int32_t)((uint32_t)kbase * 4u));
+#pragma unroll
+            for (int i = 0; i < EP; ++i) {
+                const OffT kg = k0 + 2 * pidx(t + NTHR * i);
+                const bool ok0 = o[i] >= 0 && kg < K, ok1 = o[i] >= 0 && kg + 1 < K;
+                r0[i] = buf_load<float>(rs, ok0 ? (uint32_t)(o[i] + ko0[i]) * 4u : kOutOfRange, soff);
+                r1[i] = buf_load<float>(rs, ok1 ? (uint32_t)(o[i] + ko1[i]) * 4u : kOutOfRange, soff);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < EP; ++i) {
+                const OffT kg = k0 + 2 * pidx(t + NTHR * i);
+                const bool ok0 = o[i] >= 0 && kg < K, ok1 = o[i] >= 0 && kg + 1 < K;
+                const float x0 = base[ok0 ? kbase + o[i] + ko0[i] : OffT(0)];
+                const float x1 = base[ok1 ? kbase + o[i] + ko1[i] : OffT(0)];
+                r0[i] = ok0 ? x0 : 0.f;
+                r1[i] = ok1 ? x1 : 0.f;
+            }
+        }
+    }
+    // hi plane at `hi`, lo plane at hi + PLANE (both as 32-bit words)
+    __device__ __forceinline__ void store(uint32_t* hi, int t) const {
+        uint32_t* lo = hi + PLANE / 2;
+#pragma unroll
+        for (int i = 0; i < EP; ++i) {
+            const int q = t + NTHR * i;
+            uint32_t h0, l0, h1, l1;
+            split_bf16(r0[i], h0, l0);
+            split_bf16(r1[i], h1, l1);
+            const int w = (ridx(q) * KTP + 2 * pidx(q)) >> 1;
+            hi[w] = h0 | (h1 << 16);
+            lo[w] = l0 | (l1 << 16);
+        }
+    }
+};
+
+// Regular wave grid for the split mode (KT a multiple of 32).
+template <typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
+struct TileSplit {
+    static constexpr int NTHR = WM * WN * 64;
+    static constexpr int WTM = MT / WM, WTN = NT / WN;
+    static constexpr int FM = WTM / 16, FN = WTN / 16;
+    static_assert(KT % 32 == 0, "KT must be a multiple of the bf16 matrix-core depth");
+    typedef PackPair<OffT, MT, KT, NTHR, XM> PX;
+    typedef PackPair<OffT, NT, KT, NTHR, YN> PY;
+    // one stage: X hi, X lo, Y hi, Y lo planes (in bf16 elements)
+    static constexpr int STAGE = 2 * PX::PLANE + 2 * PY::PLANE;
+    static constexpr int SMEM = 2 * STAGE / 2;  // in floats (two stages of bf16 = STAGE floats)
+
+    static __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *(const bf16x8*)p; }
+
+    static __device__ __forceinline__ void run(const KArgs<float, OffT>& a, int64_t tile, float* smemf) {
+        typedef Mfma<float> M;
+        __bf16* smem = (__bf16*)smemf;
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int wm = wave % WM, wn = wave / WM;
+        const int64_t tm = tile % a.tiles_m, tn = tile / a.tiles_m;
+        const OffT m0 = (OffT)(tm * MT), n0 = (OffT)(tn * NT);
+        PX px;
+        PY py;
+        px.init(a.rX, m0, a.m, tid);
+        py.init(a.cY, n0, a.n, tid);
+        f32x4 acc[FM][FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[i][j][r] = 0.f;
+        auto xs = [&](int buf) { return smem + buf * STAGE; };
+        auto ys = [&](int buf) { return smem + buf * STAGE + 2 * PX::PLANE; };
+        const OffT nkb = (a.k + KT - 1) / KT;
+        if (nkb > 0) {
+            px.load(a.X, a.spanX, a.cX, a.kbsX, 0, a.k, tid);
+            py.load(a.Y, a.spanY, a.rY, a.kbsY, 0, a.k, tid);
+            px.store((uint32_t*)xs(0), tid);
+            py.store((uint32_t*)ys(0), tid);
+            __syncthreads();
+            for (OffT kb = 0; kb < nkb; ++kb) {
+                const int buf = (int)(kb & 1);
+                const bool more = kb + 1 < nkb;
+                if (more) {
+                    px.load(a.X, a.spanX, a.cX, a.kbsX, kb + 1, a.k, tid);
+                    py.load(a.Y, a.spanY, a.rY, a.kbsY, kb + 1, a.k, tid);
+                }
+                const __bf16* xh = xs(buf) + (wm * WTM + (lane & 15)) * PX::KTP + 8 * (lane >> 4);
+                const __bf16* yh = ys(buf) + (wn * WTN + (lane & 15)) * PY::KTP + 8 * (lane >> 4);
+#pragma unroll
+                for (int s = 0; s < KT / 32; ++s) {
+                    bf16x8 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) {
+                        ah[i] = ld8(xh + 16 * i * PX::KTP + 32 * s);
+                        al[i] = ld8(xh + PX::PLANE + 16 * i * PX::KTP + 32 * s);
+                    }
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        bh[j] = ld8(yh + 16 * j * PY::KTP + 32 * s);
+                        bl[j] = ld8(yh + PY::PLANE + 16 * j * PY::KTP + 32 * s);
+                    }
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) {
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                        }
+                }
+                if (more) {
+                    px.store((uint32_t*)xs(buf ^ 1), tid);
+                    py.store((uint32_t*)ys(buf ^ 1), tid);
+                }
+                __syncthreads();
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                store_frag<float, OffT, M>(a, (OffT)(m0 + wm * WTM + 16 * i), (OffT)(n0 + wn * WTN + 16 * j), acc[i][j],
+                                           lane);
+    }
+};
+
+template <typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
+__global__ __launch_bounds__(WM* WN * 64) void split_kernel(KArgs<float, OffT> a) {
+    typedef TileSplit<OffT, MT, NT, KT, WM, WN, XM, YN> Tile;
+    __shared__ float smem[Tile::SMEM];
+    Tile::run(a, blockIdx.x, smem);
+}
+
+template <typename OffT, int MT, int NT, int KT, int WM, int WN>
+static int launch_split_tile(const KArgs<float, OffT>& a, bool xm, bool yn, hipStream_t s) {
+    const int64_t tiles = a.tiles_m * a.tiles_n;
+    if (tiles <= 0) return TC_OK;
+    if (tiles > 0x7fffffffLL) {
+        set_error("too many tiles for one launch");
+        return TC_ERR_ARG;
+    }
+    dim3 grid((unsigned)tiles), block(WM * WN * 64);
+    if (xm && yn) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, true, true>), grid, block, 0, s, a);
+    else if (xm) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, true, false>), grid, block, 0, s, a);
+    else if (yn) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, false, false>), grid, block, 0, s, a);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? TC_OK : hip_fail(e, "kernel launch");
+}
 
 template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT, bool XM, bool YN>
 struct TileOf {
@@ -777,10 +1017,7 @@ __global__ __launch_bounds__(256) void scale_kernel(T* C, const OffT* rC, const 
     }
 }
 
-static int hip_fail(hipError_t e, const char* what) {
-    set_error(std::string(what) + ": " + hipGetErrorString(e));
-    return TC_ERR_HIP;
-}
+
 
 template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT>
 static int launch_tile(const KArgs<T, OffT>& a, bool xm, bool yn, hipStream_t s) {
@@ -839,6 +1076,17 @@ static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, co
         return e == hipSuccess ? TC_OK : hip_fail(e, "kernel launch");
     }
     const bool xm = p.x_lanes_m, yn = p.y_lanes_n;
+    if constexpr (sizeof(T) == 4) {
+        if (p.mode == TC_SPLIT_BF16X3) {
+#define TC_SCASE(id, MT, NT, KT, WM, WN, L) \
+    case id:                                \
+        return launch_split_tile<OffT, MT, NT, KT, WM, WN>(a, xm, yn, s);
+            switch (p.tile) { TC_TILES_BF16X3(TC_SCASE) }
+#undef TC_SCASE
+            set_error("unknown tile configuration");
+            return TC_ERR_ARG;
+        }
+    }
 #define TC_CASE(id, MT, NT, KT, WM, WN, L) \
     case id:                               \
         return launch_tile<T, OffT, MT, NT, KT, WM, WN, L>(a, xm, yn, s);

@@ -24,7 +24,8 @@
     X(1, 64, 64, 32, 2, 2, 0)      \
     X(2, 128, 64, 32, 2, 2, 0)     \
     X(3, 128, 128, 32, 2, 2, 0)    \
-    X(4, 144, 144, 32, 1, 1, 1)
+    X(4, 144, 144, 32, 1, 1, 1)    \
+    X(5, 144, 144, 32, 1, 1, 2)
 
 // split-bf16: KT is a multiple of the bf16 MFMA depth (32)
 #define TC_TILES_BF16X3(X)         \

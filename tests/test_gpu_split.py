@@ -1,0 +1,111 @@
+"""Split-BF16 mode (FP32 storage, hi/lo bf16 operands, three matrix-core
+products, FP32 accumulation) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from paper_1607_00291_amd import inputs
+from gpuutil import fp32_componentwise, require_gpu, split_bf16_componentwise, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def f32(x):
+    return np.asfortranarray(np.asarray(x, dtype=np.float32).astype(np.float64))
+
+
+def run(p, mode, tile=None):
+    from paper_1607_00291_amd import tc
+    torch = require_gpu()
+    A, B, C = to_dev(p.A, np.float32), to_dev(p.B, np.float32), to_dev(p.C, np.float32)
+    plan = tc.Plan.for_tensors(A, p.idx_A, B, p.idx_B, C, p.idx_C, mode=mode)
+    if tile is not None:
+        plan.tile = tile
+    plan.execute(A, B, C, p.alpha, p.beta)
+    torch.cuda.synchronize()
+    plan.close()
+    return to_host(C).astype(np.float64)
+
+
+def oracle(oracle_mod, p, absval=False, C=None):
+    out = np.array(p.C if C is None else C, order="F", copy=True)
+    oracle_mod.contract(p.alpha if not absval else 1.0, p.A, p.idx_A, p.B, p.idx_B,
+                        p.beta if not absval else 0.0, out, p.idx_C, absval=absval)
+    return out
+
+
+def rounded(p):
+    """The problem with operands rounded to FP32 (what the GPU receives)."""
+    return inputs.Problem(p.idx_A, p.idx_B, p.idx_C, f32(p.A), f32(p.B), f32(p.C), p.alpha, p.beta, p.name,
+                          p.extents)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_split_random(oracle_mod, seed):
+    p = rounded(inputs.random_problem(5000 + seed, 2, 2, 2, lo=3, hi=20, beta=0.5 if seed % 2 else 0.0,
+                                      alpha=1.25))
+    print(f"case split random seed={seed}", flush=True)
+    got = run(p, "split_bf16x3")
+    ref = oracle(oracle_mod, p)
+    absC = oracle(oracle_mod, p, absval=True, C=np.zeros_like(p.C, order="F"))
+    bound = split_bf16_componentwise(p.mnk()[2], p.alpha, absC, p.beta, p.C)
+    assert np.all(np.abs(got - ref) <= bound + 1e-30)
+
+
+@pytest.mark.parametrize("ext", [1, 17, 45])
+def test_split_ragged_every_tile(oracle_mod, ext):
+    from paper_1607_00291_amd import tc
+    rng = np.random.default_rng(ext)
+    e = {"a": ext, "b": 5, "c": ext + 2, "d": 3, "e": ext + 1, "f": 2}
+    mk = lambda lab: f32(inputs.colmajor_from_flat(rng.uniform(-1, 1, int(np.prod(inputs.shape_of(lab, e)))),
+                                                  inputs.shape_of(lab, e)))
+    p = inputs.Problem("aebf", "dfce", "abcd", mk("aebf"), mk("dfce"), inputs.colmajor(inputs.shape_of("abcd", e), fill=0.0),
+                       1.0, 0.0, f"ragged{ext}", e)
+    ref = oracle(oracle_mod, p)
+    absC = oracle(oracle_mod, p, absval=True)
+    bound = split_bf16_componentwise(p.mnk()[2], 1.0, absC)
+    for t in range(tc.tile_count(tc.TC_F32, tc.TC_SPLIT_BF16X3)):
+        print(f"case split ragged ext={ext} tile={t}", flush=True)
+        got = run(p, "split_bf16x3", tile=t)
+        assert np.all(np.abs(got - ref) <= bound + 1e-30), t
+
+
+def test_split_integer_inputs_bitwise(oracle_mod):
+    """Small integers are exact in bf16 (lo = 0) and every partial sum is
+    exact in FP32: the split result equals the oracle bit for bit."""
+    p = inputs.random_problem(5100, 2, 2, 2, lo=2, hi=11, integer=True)
+    print("case split integer", flush=True)
+    assert np.array_equal(run(p, "split_bf16x3"), oracle(oracle_mod, p))
+
+
+@pytest.mark.parametrize("shape", ["cfg1", "cfg2"])
+def test_cfg3_fp32_and_split_error_report(oracle_mod, shape):
+    """Inputs N(0,1) with per-mode scales 10^U(-3,3): FP32 and split-BF16
+    within their bounds against the oracle on the same FP32-rounded inputs,
+    and the end-to-end error against the FP64 inputs reported."""
+    p64 = inputs.cfg3(shape=shape)
+    p = rounded(p64)
+    K = p.mnk()[2]
+    print(f"case cfg3 {shape}", flush=True)
+    if shape == "cfg1":
+        ref = oracle(oracle_mod, p)
+        absC = oracle(oracle_mod, p, absval=True)
+        ref64 = oracle(oracle_mod, p64)
+        sel = None
+    else:  # sampled outputs at the large shape
+        rng = np.random.default_rng(3)
+        sel = tuple(np.stack([rng.integers(0, n, 4096) for n in p.C.shape], axis=0))
+        pts = np.stack(sel, axis=1)
+        ref = oracle_mod.contract_points(1.0, p.A, p.idx_A, p.B, p.idx_B, 0.0, p.C, p.idx_C, pts)
+        absC = oracle_mod.contract_points(1.0, p.A, p.idx_A, p.B, p.idx_B, 0.0, p.C, p.idx_C, pts, absval=True)
+        ref64 = oracle_mod.contract_points(1.0, p64.A, p.idx_A, p64.B, p.idx_B, 0.0, p.C, p.idx_C, pts)
+    for mode, bound_fn in (("native", fp32_componentwise), ("split_bf16x3", split_bf16_componentwise)):
+        got = run(p, mode)
+        if sel is not None:
+            got = got[sel]
+        err = np.abs(got - ref)
+        bound = bound_fn(K, 1.0, absC)
+        assert np.all(err <= bound + 1e-300), mode
+        rel = np.max(np.abs(got - ref64) / np.maximum(np.abs(ref64), 1e-300))
+        ratio = np.max(err / np.maximum(bound, 1e-300))
+        print(f"{shape} {mode}: max|err| vs oracle {np.max(err):.3e}, max err/bound {ratio:.3e}, "
+              f"max rel err vs FP64 inputs {rel:.3e}", flush=True)
