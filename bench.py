@@ -1,13 +1,17 @@
-"""Benchmark: FP64 forward of the coupled-cluster-shaped contraction
-Z[abij] = sum_{k,c} W[akic] T[cbkj] + Z (a,b,c = 96; i,j,k = 24; alpha = beta = 1)
-through the C ABI, inputs resident in HBM.  Prints one JSON line.
+"""Benchmark of the transpose-free contraction on one GPU.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick] [--tile T]
 
-A step is one full contraction (one kernel launch).  The line carries the
-roofline of the contraction kernel (matrix-core bound: 2mnk flops per launch
-over the mean launch time, against the FP64 matrix peak) and the CPU oracle's
-rate on a bounded sample of the same workload.
+Headline workload (value, roofline): the FP64 forward of the coupled-cluster
+shaped contraction Z[abij] = sum_{k,c} W[akic] T[cbkj] + Z with a,b,c = 96 and
+i,j,k = 24 (alpha = beta = 1), inputs resident in HBM.  A step is one full
+contraction (one kernel launch); value = 2mnk / mean step time.
+
+The same line carries, under "secondary", the other workloads measured on the
+same GPU: FP32 and split-BF16 at the same shape, the FP32 forward + backward of
+C[ijab] = A[iklb] B[kjal] (i,j,k,l = 32, a,b = 64), the FP64 extent-16
+contraction C[abcd] = A[aebf] B[dfce], and 512 batched FP64 contractions in one
+persistent launch against 512 sequential launches (unless --quick).
 """
 import argparse
 import hashlib
@@ -24,20 +28,22 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
-HBM_PEAK_GBS = 8000.0
+WORKLOAD = "Z[abij]+=W[akic]T[cbkj] v=96 o=24 fp64"
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1607_00291_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_1607_00291_amd", "csrc", f), "rb") as fh:
+    d = os.path.join(ROOT, "paper_1607_00291_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload_key, launches_per_step=1):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when the kernel sources changed since the counters were taken."""
+def load_traffic(workload_key):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None when the kernel sources changed since
+    the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as fh:
@@ -63,13 +69,159 @@ def cpu_baseline(p, target_s=12.0):
         oracle.contract_points(p.alpha, p.A, p.idx_A, p.B, p.idx_B, p.beta, p.C, p.idx_C, pts, threads=threads)
         return time.perf_counter() - t0
 
-    n = 2048
+    n = 4096
     t = run(n)
-    n2 = int(min(max(n * target_s / max(t, 1e-3), n), 4_000_000))
+    n2 = int(min(max(n * target_s / max(t, 1e-3), n), 20_000_000))
     t2 = run(n2)
     flops = 2.0 * K * n2
     return {"value": round(flops / t2 / 1e9, 4), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{n2} random output elements of Z, each a full K={K} FP64 sum ({t2:.1f} s)"}
+
+
+def dev(a, dtype=None):
+    """Device tensor with the numpy array's shape and element strides."""
+    import torch
+    a = np.asarray(a) if dtype is None else np.asarray(a).astype(dtype, order="K")
+    strides = [s // a.itemsize for s in a.strides]
+    span = 1 + sum((d - 1) * s for d, s in zip(a.shape, strides)) if a.size else 1
+    base = torch.zeros(span, dtype=torch.from_numpy(np.zeros(1, a.dtype)).dtype, device="cuda")
+    t = torch.as_strided(base, a.shape, strides)
+    if a.size:
+        t.copy_(torch.from_numpy(np.ascontiguousarray(a).reshape(a.shape)).cuda())
+    return t
+
+
+def time_calls(fn, steps, warmup):
+    """Mean milliseconds per call, hipEvent timing on the current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def plan_runner(tc, A, ia, B, ib, C, ic, alpha, beta, mode="native"):
+    import torch
+    plan = tc.Plan.for_tensors(A, ia, B, ib, C, ic, mode=mode)
+    plan.upload()
+    lib, h = tc.lib(), plan.handle
+    Ap, Bp, Cp = A.data_ptr(), B.data_ptr(), C.data_ptr()
+    sp = torch.cuda.current_stream().cuda_stream
+
+    def run():
+        tc._check(lib.tc_plan_execute(h, alpha, Ap, Bp, beta, Cp, sp))
+    return plan, run
+
+
+def secondary(tc, inputs, steps, warmup, quick):
+    import torch
+    out = {}
+    # FP32 and split-BF16 at the v=96/o=24 shape
+    p = inputs.cfg2()
+    m, n, k = p.mnk()
+    fl = 2.0 * m * n * k
+    A, B, C = dev(p.A, np.float32), dev(p.B, np.float32), dev(p.C, np.float32)
+    for mode, peak, mult in (("native", PEAK_FP32_TFLOPS, 1), ("split_bf16x3", PEAK_BF16_TFLOPS, 3)):
+        plan, run = plan_runner(tc, A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 1.0, mode)
+        ms = time_calls(run, steps, warmup)
+        d = plan.describe()
+        key = "fp32_v96_o24" if mode == "native" else "split_bf16_v96_o24"
+        out[key] = {"gflops": round(fl / ms / 1e6, 1), "ms": round(ms, 4),
+                    "frac_of_peak": round(mult * fl / ms / 1e9 / peak, 4),
+                    "peak_tflops": peak, "tile": [d["MT"], d["NT"], d["KT"]]}
+        if mult == 3:
+            out[key]["note"] = "frac counts the three bf16 products (3 * 2mnk) against the dense bf16 peak"
+        plan.close()
+    del A, B, C
+    # FP32 forward + backward, C[ijab] = A[iklb] B[kjal]
+    p = inputs.cfg4()
+    A, B, dC = dev(p.A, np.float32), dev(p.B, np.float32), dev(p.dC, np.float32)
+    C = dev(p.C, np.float32)
+    dA = dev(np.zeros_like(p.A, order="F"), np.float32)
+    dB = dev(np.zeros_like(p.B, order="F"), np.float32)
+    runs = {
+        "fwd": plan_runner(tc, A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 0.0),
+        "dA": plan_runner(tc, dC, p.idx_C, B, p.idx_B, dA, p.idx_A, 1.0, 0.0),
+        "dB": plan_runner(tc, A, p.idx_A, dC, p.idx_C, dB, p.idx_B, 1.0, 0.0),
+    }
+    fl4 = 2.0 * 2048 * 2048 * 1024
+    rec = {}
+    tot = 0.0
+    for name, (plan, run) in runs.items():
+        ms = time_calls(run, steps, warmup)
+        tot += ms
+        rec[name] = {"gflops": round(fl4 / ms / 1e6, 1), "ms": round(ms, 4),
+                     "frac_of_fp32_peak": round(fl4 / ms / 1e9 / PEAK_FP32_TFLOPS, 4)}
+        plan.close()
+    rec["fwd_bwd"] = {"gflops": round(3 * fl4 / tot / 1e6, 1), "ms": round(tot, 4),
+                      "frac_of_fp32_peak": round(3 * fl4 / tot / 1e9 / PEAK_FP32_TFLOPS, 4)}
+    # the same through torch.autograd (Contract.apply + backward)
+    from paper_1607_00291_amd.autograd import contract
+    Ag = A.detach().requires_grad_(True)
+    Bg = B.detach().requires_grad_(True)
+
+    def fb():
+        Ag.grad = None
+        Bg.grad = None
+        contract(Ag, p.idx_A, Bg, p.idx_B, p.idx_C).backward(dC)
+    ms = time_calls(fb, max(steps // 2, 3), 2)
+    rec["autograd_fwd_bwd"] = {"gflops": round(3 * fl4 / ms / 1e6, 1), "ms": round(ms, 4)}
+    out["fp32_fwd_bwd_ijab_iklb_kjal"] = rec
+    del A, B, C, dA, dB, dC, Ag, Bg
+    # FP64 extent-16 contraction (latency-bound)
+    p = inputs.cfg1()
+    A, B, C = dev(p.A), dev(p.B), dev(p.C)
+    plan, run = plan_runner(tc, A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 0.0)
+    ms = time_calls(run, steps * 4, warmup)
+    out["fp64_abcd_aebf_dfce_x16"] = {"us_per_call": round(ms * 1e3, 2), "gflops": round(p.flops() / ms / 1e6, 1)}
+    plan.close()
+    del A, B, C
+    if not quick:
+        out["batched_512_fp64"] = batched(tc, inputs, steps, warmup)
+    torch.cuda.empty_cache()
+    return out
+
+
+def batched(tc, inputs, steps, warmup):
+    """512 contractions (extents 4..64, random permutations) in one
+    persistent launch against 512 sequential plan launches."""
+    import torch
+    probs, tensors, total = [], [], 0.0
+    for i in range(512):
+        p = inputs.cfg5_instance(i)
+        A, B, C = dev(p.A), dev(p.B), dev(p.C)
+        probs.append(p)
+        tensors.append((A, B, C))
+        total += p.flops()
+    batch = tc.Batch([(A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 0.0) for p, (A, B, C) in zip(probs, tensors)])
+    tile, _ = batch.autotune(reps=2)
+    ms_b = time_calls(batch.execute, max(steps // 5, 3), 1)
+    plans = [plan_runner(tc, A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 0.0) for p, (A, B, C) in zip(probs, tensors)]
+
+    def seq():
+        for _, run in plans:
+            run()
+    ms_s = time_calls(seq, max(steps // 5, 3), 1)
+    info = batch.info()
+    for plan, _ in plans:
+        plan.close()
+    batch.close()
+    del tensors
+    torch.cuda.empty_cache()
+    return {"problems": 512, "total_gflop": round(total / 1e9, 1), "batched_ms": round(ms_b, 3),
+            "sequential_ms": round(ms_s, 3), "speedup": round(ms_s / ms_b, 3),
+            "batched_gflops": round(total / ms_b / 1e6, 1),
+            "batched_frac_of_fp64_peak": round(total / ms_b / 1e9 / PEAK_FP64_TFLOPS, 4),
+            "sequential_gflops": round(total / ms_s / 1e6, 1), "batch_tile": tile,
+            "work_items": info["work_items"], "grid": info["grid"]}
 
 
 def main():
@@ -78,8 +230,20 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true", help="headline workload only (no secondary workloads)")
     ap.add_argument("--tile", type=int, default=None, help="force a tile configuration")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -93,49 +257,22 @@ def main():
     p = inputs.cfg2()
     m, n, k = p.mnk()
     flops = 2.0 * m * n * k
-
-    def dev(a):
-        strides = [s // a.itemsize for s in a.strides]
-        span = 1 + sum((d - 1) * s for d, s in zip(a.shape, strides))
-        base = torch.zeros(span, dtype=torch.float64, device="cuda")
-        t = torch.as_strided(base, a.shape, strides)
-        t.copy_(torch.from_numpy(np.ascontiguousarray(a)).cuda())
-        return t
-
     W, T, Z = dev(p.A), dev(p.B), dev(p.C)
-    plan = tc.Plan.for_tensors(W, p.idx_A, T, p.idx_B, Z, p.idx_C)
+    plan, run = plan_runner(tc, W, p.idx_A, T, p.idx_B, Z, p.idx_C, p.alpha, p.beta)
     if args.tile is not None:
         plan.tile = args.tile
-    plan.upload()
+        plan.upload()
     desc = plan.describe()
-    stream = torch.cuda.current_stream()
-    sp = stream.cuda_stream
-    h = plan.handle
-    lib = tc.lib()
-    alpha, beta = p.alpha, p.beta
-    Wp, Tp, Zp = W.data_ptr(), T.data_ptr(), Z.data_ptr()
-
-    for _ in range(args.warmup):
-        tc._check(lib.tc_plan_execute(h, alpha, Wp, Tp, beta, Zp, sp))
-    torch.cuda.synchronize()
-
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
     t_wall = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        tc._check(lib.tc_plan_execute(h, alpha, Wp, Tp, beta, Zp, sp))
-    e1.record(stream)
-    torch.cuda.synchronize()
+    ms = time_calls(run, args.steps, args.warmup)
     wall = time.perf_counter() - t_wall
-    ms = e0.elapsed_time(e1) / args.steps
     gflops = flops / (ms * 1e-3) / 1e9
     achieved_tf = gflops / 1e3
+    plan.close()
+    del W, T, Z
 
-    workload = "Z[abij]+=W[akic]T[cbkj] v=96 o=24 fp64"
-    traffic = load_traffic(workload)
     line = {
-        "metric": "contraction GFLOP/s (FP64 forward, % of FP64 matrix-core peak in roofline)",
+        "metric": "contraction GFLOP/s (FP64 forward; % of FP64 matrix-core peak in roofline)",
         "value": round(gflops, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -147,17 +284,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded normal inputs, column-major)",
-        "config": {"workload": workload, "m": m, "n": n, "k": k, "alpha": alpha, "beta": beta,
+        "config": {"workload": WORKLOAD, "m": m, "n": n, "k": k, "alpha": p.alpha, "beta": p.beta,
                    "tile": [desc["MT"], desc["NT"], desc["KT"]], "waves": desc["waves"],
                    "x_lanes": desc["x_lanes"], "y_lanes": desc["y_lanes"], "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
-                     "algorithmic_flops_per_launch": flops, "mean_launch_ms": round(ms, 5)},
+                     "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4),
+                     "traffic": load_traffic(WORKLOAD), "algorithmic_flops_per_launch": flops,
+                     "mean_launch_ms": round(ms, 5)},
         "wall_s_timed_region": round(wall, 3),
     }
+    if not args.quick:
+        line["secondary"] = secondary(tc, inputs, max(args.steps // 5, 5), 2, False)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p)
-    plan.close()
     print(json.dumps(line), flush=True)
 
 

@@ -179,6 +179,27 @@ __device__ __forceinline__ int64_t uniform(int64_t x) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
+// XCDs (workgroup w runs on XCD w % 8), each with its own L2.  Workgroup w is
+// given tile g = (w % 8) * T/8 + w / 8 of a grouped enumeration that walks
+// G rows of tiles at a time (tm fastest inside a group), so every XCD works
+// on a compact G x (T/8G) block and reads about G + T/(8G) operand panels
+// instead of (for the plain column-major order) a few rows and every column.
+// Identity when T is not a multiple of 8 or too small to matter.
+__device__ __forceinline__ int64_t xcd_tile(int64_t w, int64_t tiles_m, int64_t tiles_n) {
+    const int64_t T = tiles_m * tiles_n;
+    if (T % 8 != 0 || T < 64) return w;
+    const int64_t c = T / 8;
+    const int64_t g = (w % 8) * c + w / 8;
+    int64_t G = 1;
+    while (G * G * 4 <= c && G * 2 <= tiles_m) G *= 2;  // G ~ sqrt(c), a power of two
+    const int64_t per = G * tiles_n;
+    const int64_t grp = g / per, within = g % per;
+    const int64_t gh = (tiles_m - grp * G) < G ? (tiles_m - grp * G) : G;
+    const int64_t tm = grp * G + within % gh, tn = within / gh;
+    return tm + tiles_m * tn;
+}
+
 // Bounds-checked buffer loads (32-bit-offset plans): a byte offset at or past
 // the buffer's size reads 0, so ragged edges need no select after the load
 // and every load of a stage can stay in flight until the LDS write.
@@ -445,127 +466,6 @@ struct TileRegular {
     }
 };
 
-// Pinwheel layout for MT = NT = 144 on four waves: the 9 x 9 grid of 16 x 16
-// fragments is covered by four rectangles of 20 fragments (4x5 at (0,0), 5x4
-// at (0,5), 4x5 at (5,4), 5x4 at (4,0)) around the centre fragment (4,4),
-// whose k-steps are dealt round-robin to the four waves and summed in LDS at
-// the end.  Every SIMD then issues exactly 20.25 fragment updates per k-step,
-// and a 2304 x 2304 output is exactly 256 tiles, one per compute unit.
-template <typename T, typename OffT, int KT, bool XM, bool YN>
-struct TilePinwheel {
-    static constexpr int MT = 144, NT = 144, NTHR = 256;
-    static_assert(KT % 16 == 0, "the centre k-split needs KT a multiple of 16");
-    typedef Pack<T, OffT, MT, NT, KT, NTHR, XM, YN> P;
-    static constexpr int SMEM = P::ELEMS > 4 * 256 ? P::ELEMS : 4 * 256;
-
-    template <int R, int C>
-    static __device__ __forceinline__ void step(typename Mfma<T>::acc_t* acc, const T* bx, const T* by, int kr, int fr0,
-                                                int fc0, int lane) {
-        typedef Mfma<T> M;
-        typename M::afrag fa[R];
-        typename M::bfrag fb[C];
-#pragma unroll
-        for (int i = 0; i < R; ++i) fa[i] = M::load_a(bx + kr * P::LDX + 16 * (fr0 + i), lane);
-#pragma unroll
-        for (int j = 0; j < C; ++j) fb[j] = M::load_b(by + kr * P::LDY + 16 * (fc0 + j), lane);
-#pragma unroll
-        for (int i = 0; i < R; ++i)
-#pragma unroll
-            for (int j = 0; j < C; ++j) M::run(fa[i], fb[j], acc[i * C + j]);
-    }
-
-    template <int R, int C>
-    static __device__ __forceinline__ void step2(typename Mfma<T>::acc_t* acc, const T* bx, const T* by, int kr, int fr0,
-                                                 int fc0, int lane, int ldx, int ldy) {
-        typedef Mfma<T> M;
-        typename M::afrag fa[R];
-        typename M::bfrag fb[C];
-#pragma unroll
-        for (int i = 0; i < R; ++i) fa[i] = M::load_a(bx + kr * ldx + 16 * (fr0 + i), lane);
-#pragma unroll
-        for (int j = 0; j < C; ++j) fb[j] = M::load_b(by + kr * ldy + 16 * (fc0 + j), lane);
-#pragma unroll
-        for (int i = 0; i < R; ++i)
-#pragma unroll
-            for (int j = 0; j < C; ++j) M::run(fa[i], fb[j], acc[i * C + j]);
-    }
-
-    template <int R, int C>
-    static __device__ __forceinline__ void epilogue(const KArgs<T, OffT>& a, const typename Mfma<T>::acc_t* acc,
-                                                    OffT m0, OffT n0, int fr0, int fc0, int lane) {
-#pragma unroll
-        for (int i = 0; i < R; ++i)
-#pragma unroll
-            for (int j = 0; j < C; ++j)
-                store_frag(a, (OffT)(m0 + 16 * (fr0 + i)), (OffT)(n0 + 16 * (fc0 + j)), acc[i * C + j], lane);
-    }
-
-    static __device__ __forceinline__ void run(const KArgs<T, OffT>& a, int64_t tile, T* smem) {
-        typedef Mfma<T> M;
-        typedef typename M::acc_t acc_t;
-        const int tid = threadIdx.x;
-        const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-        // rectangle of this wave (in fragments)
-        const bool wide = (wave & 1) == 0;  // 4 x 5 for waves 0 and 2, 5 x 4 for 1 and 3
-        const int fr0 = wave == 2 ? 5 : wave == 3 ? 4 : 0;
-        const int fc0 = wave == 1 ? 5 : wave == 2 ? 4 : 0;
-        const int64_t tm = tile % a.tiles_m, tn = tile / a.tiles_m;
-        const OffT m0 = (OffT)(tm * MT), n0 = (OffT)(tn * NT);
-
-        P pk;
-        pk.init(a, m0, n0, tid);
-        acc_t acc[20], accc;
-#pragma unroll
-        for (int f = 0; f < 20; ++f)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc[f][r] = T(0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) accc[r] = T(0);
-
-        const OffT nkb = (a.k + KT - 1) / KT;
-        if (nkb > 0) {
-            pk.load(a, 0, tid);
-            pk.store(smem, 0, tid);
-            __syncthreads();
-            for (OffT kb = 0; kb < nkb; ++kb) {
-                const int buf = (int)(kb & 1);
-                const bool more = kb + 1 < nkb;
-                if (more) pk.load(a, kb + 1, tid);
-                const T* bx = smem + buf * P::XS;
-                const T* by = smem + 2 * P::XS + buf * P::YS;
-#pragma unroll
-                for (int s = 0; s < KT / 4; ++s) {
-                    const int kr = 4 * s + (lane >> 4);
-                    if (wide) step<4, 5>(acc, bx, by, kr, fr0, fc0, lane);
-                    else step<5, 4>(acc, bx, by, kr, fr0, fc0, lane);
-                    if ((s & 3) == wave)
-                        M::run(M::load_a(bx + kr * P::LDX + 64, lane), M::load_b(by + kr * P::LDY + 64, lane), accc);
-                }
-                if (more) pk.store(smem, buf ^ 1, tid);
-                __syncthreads();
-            }
-        }
-        if (wide) epilogue<4, 5>(a, acc, m0, n0, fr0, fc0, lane);
-        else epilogue<5, 4>(a, acc, m0, n0, fr0, fc0, lane);
-        // centre fragment: partial sums of the four waves added in wave order
-#pragma unroll
-        for (int r = 0; r < 4; ++r) smem[wave * 256 + r * 64 + lane] = accc[r];
-        __syncthreads();
-        if (wave == 0) {
-            acc_t v;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                T x = smem[r * 64 + lane];
-                x += smem[256 + r * 64 + lane];
-                x += smem[512 + r * 64 + lane];
-                x += smem[768 + r * 64 + lane];
-                v[r] = x;
-            }
-            store_frag(a, (OffT)(m0 + 64), (OffT)(n0 + 64), v, lane);
-        }
-    }
-};
-
 // The pack stage of one operand, with the operand (and so the lane
 // direction and LDS pitch) chosen at run time: used where a wave gathers
 // either X or Y, so that only one set of gather registers is live.
@@ -635,10 +535,15 @@ struct PackRole {
     }
 };
 
-// Pinwheel layout on eight waves (two per SIMD): each rectangle of the
-// four-wave pinwheel is halved (2x5 or 5x2 fragments per wave) and the centre
-// fragment's k-steps are dealt round-robin over the eight waves.  Waves 0-3
-// gather the X sliver and waves 4-7 the Y sliver of each stage.
+// Pinwheel layout for MT = NT = 144 on eight waves (two per SIMD).  The 9 x 9
+// grid of 16 x 16 fragments minus its centre fragment (4,4) is covered by
+// four 4x5 / 5x4 rectangles arranged as a pinwheel around it (4x5 at (0,0),
+// 5x4 at (0,5), 4x5 at (5,4), 5x4 at (4,0)); each wave owns half a rectangle
+// (2 x 5 or 5 x 2 fragments) and the centre fragment's k-steps are dealt
+// round-robin over the eight waves and summed in LDS at the end.  Every SIMD
+// then issues exactly 20.25 fragment updates per k-step, and a 2304 x 2304
+// output is exactly 256 tiles, one per compute unit.  Waves 0-3 gather the X
+// sliver and waves 4-7 the Y sliver of each stage.
 template <typename T, typename OffT, int KT, bool XM, bool YN>
 struct TilePinwheel8 {
     static constexpr int MT = 144, NT = 144, NTHR = 512;
@@ -717,6 +622,9 @@ struct TilePinwheel8 {
                 const int kr = 4 * s + kr0;
                 rect_step<T, MW, 2, 5>(acc, bp + kr * ldp, bq + kr * ldq, p0, q0, lane);
                 if (cs == s) M::run(ca, cb, accc);
+                // the next stage goes to the other LDS buffer (last read before
+                // the previous barrier) while this stage's k-steps run, so the
+                // LDS writes overlap the matrix-core work
             }
             if (kb + 1 < nkb) pk.template store<(SL + 1) % SLOTS>(gstage + (buf ^ 1) * gsz, tt);
             __syncthreads();
@@ -962,7 +870,7 @@ template <typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool Y
 __global__ __launch_bounds__(WM* WN * 64) void split_kernel(KArgs<float, OffT> a) {
     typedef TileSplit<OffT, MT, NT, KT, WM, WN, XM, YN> Tile;
     __shared__ float smem[Tile::SMEM];
-    Tile::run(a, blockIdx.x, smem);
+    Tile::run(a, xcd_tile(blockIdx.x, a.tiles_m, a.tiles_n), smem);
 }
 
 template <typename OffT, int MT, int NT, int KT, int WM, int WN>
@@ -989,11 +897,6 @@ struct TileOf {
 };
 template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
 struct TileOf<T, OffT, MT, NT, KT, WM, WN, 1, XM, YN> {
-    typedef TilePinwheel<T, OffT, KT, XM, YN> type;
-    static constexpr int threads = 256;
-};
-template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
-struct TileOf<T, OffT, MT, NT, KT, WM, WN, 2, XM, YN> {
     typedef TilePinwheel8<T, OffT, KT, XM, YN> type;
     static constexpr int threads = 512;
 };
@@ -1003,7 +906,7 @@ __global__ __launch_bounds__((TileOf<T, OffT, MT, NT, KT, WM, WN, LAYOUT, XM, YN
     KArgs<T, OffT> a) {
     typedef typename TileOf<T, OffT, MT, NT, KT, WM, WN, LAYOUT, XM, YN>::type Tile;
     __shared__ T smem[Tile::SMEM];
-    Tile::run(a, blockIdx.x, smem);
+    Tile::run(a, xcd_tile(blockIdx.x, a.tiles_m, a.tiles_n), smem);
 }
 
 // C := beta * C over the matrix view (k == 0 or alpha == 0).

@@ -4,11 +4,12 @@
 // Columns: id, MT, NT, KT, WM, WN, LAYOUT
 //   MT x NT  output tile of one workgroup, KT the k-depth of one LDS stage
 //   WM x WN  grid of 64-lane waves; each wave owns (MT/WM) x (NT/WN) outputs
-//   LAYOUT   0 = regular wave grid; 1 = "pinwheel": 4 waves on a 9x9 grid of
-//            16x16 fragments, four 4x5 / 5x4 rectangles around the centre
-//            fragment whose k-range is split over the 4 waves, so that every
-//            SIMD does exactly 20.25 fragments of work; 2 = the same on 8
-//            waves (two per SIMD), each owning half a rectangle
+//   LAYOUT   0 = regular wave grid; 1 = "pinwheel" (MT = NT = 144, eight
+//            waves): four 4x5 / 5x4 rectangles of 16x16 fragments around the
+//            centre fragment of the 9x9 grid, each halved between two waves,
+//            the centre's k-range split over the eight waves, so that every
+//            SIMD does exactly 20.25 fragments of work and 2304^2 outputs
+//            make exactly 256 tiles
 #pragma once
 
 #define TC_TILES_F64(X)            \
@@ -16,16 +17,14 @@
     X(1, 64, 64, 16, 2, 2, 0)      \
     X(2, 128, 64, 16, 2, 2, 0)     \
     X(3, 128, 128, 16, 2, 2, 0)    \
-    X(4, 144, 144, 16, 1, 1, 1)    \
-    X(5, 144, 144, 16, 1, 1, 2)
+    X(4, 144, 144, 16, 1, 1, 1)
 
 #define TC_TILES_F32(X)            \
     X(0, 32, 32, 32, 1, 1, 0)      \
     X(1, 64, 64, 32, 2, 2, 0)      \
     X(2, 128, 64, 32, 2, 2, 0)     \
     X(3, 128, 128, 32, 2, 2, 0)    \
-    X(4, 144, 144, 32, 1, 1, 1)    \
-    X(5, 144, 144, 32, 1, 1, 2)
+    X(4, 144, 144, 32, 1, 1, 1)
 
 // split-bf16: KT is a multiple of the bf16 MFMA depth (32)
 #define TC_TILES_BF16X3(X)         \
@@ -38,7 +37,7 @@ namespace tc {
 
 struct TileCfg {
     int MT, NT, KT, WM, WN, layout;
-    int waves() const { return layout == 1 ? 4 : layout == 2 ? 8 : WM * WN; }
+    int waves() const { return layout == 1 ? 8 : WM * WN; }
 };
 
 #define TC_TILE_ENTRY(id, MT, NT, KT, WM, WN, L) TileCfg{MT, NT, KT, WM, WN, L},

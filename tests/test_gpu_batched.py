@@ -55,7 +55,7 @@ def test_batched_every_tile_and_graph_replay(oracle_mod):
     ref = None
     for t in range(tc.tile_count(tc.TC_F64)):
         MT, NT, KT, waves = tc.tile_info(tc.TC_F64, tc.TC_NATIVE, t)
-        if MT == 144:  # pinwheel layouts are single-problem only
+        if MT == 144:  # the pinwheel layout is single-problem only
             continue
         batch.tile = t
         for _, _, C in dev:
