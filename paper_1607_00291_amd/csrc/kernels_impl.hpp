@@ -622,9 +622,6 @@ struct TilePinwheel8 {
                 const int kr = 4 * s + kr0;
                 rect_step<T, MW, 2, 5>(acc, bp + kr * ldp, bq + kr * ldq, p0, q0, lane);
                 if (cs == s) M::run(ca, cb, accc);
-                // the next stage goes to the other LDS buffer (last read before
-                // the previous barrier) while this stage's k-steps run, so the
-                // LDS writes overlap the matrix-core work
             }
             if (kb + 1 < nkb) pk.template store<(SL + 1) % SLOTS>(gstage + (buf ^ 1) * gsz, tt);
             __syncthreads();
