@@ -575,6 +575,8 @@ static int batch_create(tc_batch** out, int count, const tc_plan* const* plans, 
         it.beta = beta[i];
         it.x_lanes_m = p.x_lanes_m;
         it.y_lanes_n = p.y_lanes_n;
+        it.kregX = p.k_blocks_regular_x == (int64_t)p.kbsX.size();
+        it.kregY = p.k_blocks_regular_y == (int64_t)p.kbsY.size();
         b->host.push_back(it);
     }
     if (total) {

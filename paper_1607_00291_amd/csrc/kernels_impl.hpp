@@ -159,6 +159,7 @@ struct KArgs {
     int64_t tiles_m, tiles_n;
     int64_t spanX, spanY;  // element spans of X and Y (bounds of the buffer loads)
     T alpha, beta;
+    int kregX, kregY;  // 1: every k block of X (Y) has a nonzero block stride
 };
 
 // LDS row pitch (in elements) of a k-major stage: one element of padding when
@@ -492,12 +493,23 @@ struct PackRole {
     template <int SL = 0>
     __device__ __forceinline__ void load(const T* base, int64_t span, const OffT* kvec, const OffT* kbs, OffT kb, OffT K,
                                          int t) {
+        load_with<SL>(uniform(kbs[kb]), uniform(kvec[kb * KT]), base, span, kvec, kb, K, t);
+    }
+    // The same with the k block's stride and first k offset already in
+    // scalar registers (fetched ahead by the caller).  REG = 1: the caller
+    // knows every k block of this operand has a nonzero stride (no per-k
+    // offset reads); REG = 0: always read the per-k offsets (right for any
+    // block); REG = -1: decide per block.  A compile-time choice keeps the
+    // per-k offset reads (vector memory loads) off the regular path, so the
+    // counter waits they need do not hold back gathers already in flight.
+    template <int SL = 0, int REG = -1>
+    __device__ __forceinline__ void load_with(OffT sk, OffT kfirst, const T* base, int64_t span, const OffT* kvec,
+                                              OffT kb, OffT K, int t) {
         const OffT k0 = kb * KT;
-        const OffT sk = uniform(kbs[kb]);
         OffT ko[E];
         OffT kbase = 0;
-        if (sk) {
-            kbase = uniform(kvec[k0]);
+        if (REG == 1 || (REG == -1 && sk)) {
+            kbase = kfirst;
 #pragma unroll
             for (int i = 0; i < E; ++i) ko[i] = (OffT)kidx(t + NTHR * i) * sk;
         } else {
@@ -597,50 +609,79 @@ struct TilePinwheel8 {
         // the gathers of stage kb + 2 are in flight in one register slot and
         // stage kb + 1 (gathered one iteration earlier) goes from the other
         // slot to LDS, so each gather has two stages of compute to land.
-        auto body = [&](OffT kb, auto slot) {
+        // block stride and first k offset of the next gather, fetched one
+        // stage ahead so their scalar-load latency is hidden
+        OffT pre_sk = 0, pre_k = 0;
+        auto fetch = [&](OffT kb) {
+            pre_sk = uniform(gbs[kb]);
+            pre_k = uniform(gk[kb * KT]);
+        };
+        // Every stage issues its gathers and its LDS store with no branch
+        // around them: a gather past the last stage re-reads the last stage
+        // and is stored into the LDS buffer no stage reads any more, and with
+        // two slots an odd stage count ends with one stage that only moves
+        // data.  The counter waits the compiler places then see the same
+        // memory operations in flight on every path, and the gathers of later
+        // stages stay in flight over the compute.
+        auto body = [&](OffT kb, auto slot, auto reg) {
             constexpr int SL = decltype(slot)::value;
+            constexpr int RG = decltype(reg)::value;
             constexpr int AHEAD = SLOTS;  // stages between a gather and its use
             const int buf = (int)(kb & 1);
-            if (kb + AHEAD < nkb) pk.template load<SL>(gbase, gspan, gk, gbs, kb + AHEAD, a.k, tt);
-            const T* bx = smem + buf * XS;
-            const T* by = smem + 2 * XS + buf * YS;
-            // a 5 x 2 rectangle of C is run as the 2 x 5 rectangle of C^T:
-            // the Y stage feeds the A side and the X stage the B side
-            const T* bp = wide ? bx : by;
-            const T* bq = wide ? by : bx;
-            typename M::afrag ca;
-            typename M::bfrag cb;
-            const int kr0 = lane >> 4;
-            // the centre fragment's k-steps go round-robin over the waves
-            const int cs = (wave - (int)((kb * (KT / 4)) & 7)) & 7;  // this wave's centre k-step, if < KT/4
-            if (cs < KT / 4) {
-                ca = M::load_a(bx + (4 * cs + kr0) * LDX + 64, lane);
-                cb = M::load_b(by + (4 * cs + kr0) * LDY + 64, lane);
-            }
+            const OffT lk = kb + AHEAD < nkb ? kb + AHEAD : nkb - 1;
+            pk.template load_with<SL, RG>(pre_sk, pre_k, gbase, gspan, gk, lk, a.k, tt);
+            fetch(kb + AHEAD + 1 < nkb ? kb + AHEAD + 1 : nkb - 1);
+            if (kb < nkb) {
+                const T* bx = smem + buf * XS;
+                const T* by = smem + 2 * XS + buf * YS;
+                // a 5 x 2 rectangle of C is run as the 2 x 5 rectangle of C^T:
+                // the Y stage feeds the A side and the X stage the B side
+                const T* bp = wide ? bx : by;
+                const T* bq = wide ? by : bx;
+                typename M::afrag ca;
+                typename M::bfrag cb;
+                const int kr0 = lane >> 4;
+                // the centre fragment's k-steps go round-robin over the waves
+                const int cs = (wave - (int)((kb * (KT / 4)) & 7)) & 7;  // this wave's centre k-step, if < KT/4
+                if (cs < KT / 4) {
+                    ca = M::load_a(bx + (4 * cs + kr0) * LDX + 64, lane);
+                    cb = M::load_b(by + (4 * cs + kr0) * LDY + 64, lane);
+                }
 #pragma unroll
-            for (int s = 0; s < KT / 4; ++s) {
-                const int kr = 4 * s + kr0;
-                rect_step<T, MW, 2, 5>(acc, bp + kr * ldp, bq + kr * ldq, p0, q0, lane);
-                if (cs == s) M::run(ca, cb, accc);
+                for (int s = 0; s < KT / 4; ++s) {
+                    const int kr = 4 * s + kr0;
+                    rect_step<T, MW, 2, 5>(acc, bp + kr * ldp, bq + kr * ldq, p0, q0, lane);
+                    if (cs == s) M::run(ca, cb, accc);
+                }
             }
-            if (kb + 1 < nkb) pk.template store<(SL + 1) % SLOTS>(gstage + (buf ^ 1) * gsz, tt);
+            pk.template store<(SL + 1) % SLOTS>(gstage + (buf ^ 1) * gsz, tt);
             __syncthreads();
         };
-        if (nkb > 0) {
-            pk.template load<0>(gbase, gspan, gk, gbs, 0, a.k, tt);
+        typedef std::integral_constant<int, 0> S0;
+        typedef std::integral_constant<int, 1> S1;
+        auto pipeline = [&](auto reg) {
+            constexpr int RG = decltype(reg)::value;
+            fetch(0);
+            pk.template load_with<0, RG>(pre_sk, pre_k, gbase, gspan, gk, 0, a.k, tt);
             pk.template store<0>(gstage, tt);
             if constexpr (SLOTS == 2) {
-                if (nkb > 1) pk.template load<1>(gbase, gspan, gk, gbs, 1, a.k, tt);
+                fetch(nkb > 1 ? 1 : 0);
+                pk.template load_with<1, RG>(pre_sk, pre_k, gbase, gspan, gk, nkb > 1 ? 1 : 0, a.k, tt);
             }
+            fetch(nkb > SLOTS ? SLOTS : nkb - 1);
             __syncthreads();
             if constexpr (SLOTS == 2) {
                 for (OffT kb = 0; kb < nkb; kb += 2) {
-                    body(kb, std::integral_constant<int, 0>());
-                    if (kb + 1 < nkb) body(kb + 1, std::integral_constant<int, 1>());
+                    body(kb, S0(), reg);
+                    body(kb + 1, S1(), reg);
                 }
             } else {
-                for (OffT kb = 0; kb < nkb; ++kb) body(kb, std::integral_constant<int, 0>());
+                for (OffT kb = 0; kb < nkb; ++kb) body(kb, S0(), reg);
             }
+        };
+        if (nkb > 0) {
+            if (gx ? a.kregX : a.kregY) pipeline(std::integral_constant<int, 1>());
+            else pipeline(std::integral_constant<int, 0>());
         }
         if (wide) rect_store<T, OffT, MW, 2, 5>(a, acc, m0, n0, fr0, fc0, lane);
         else rect_store_t<T, OffT, MW, 2, 5>(a, acc, m0, n0, fc0, fr0, lane);
@@ -675,19 +716,21 @@ struct TilePinwheel8 {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// round-to-nearest-even FP32 -> bf16 bits; NaN stays NaN
-__device__ __forceinline__ uint32_t bf16_bits(float x) {
-    const uint32_t u = __builtin_bit_cast(uint32_t, x);
-    if (x != x) return 0x7fc0u;
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-__device__ __forceinline__ float bf16_value(uint32_t h) { return __builtin_bit_cast(float, h << 16); }
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-// hi and lo halves of x (lo = 0 when x is not finite)
-__device__ __forceinline__ void split_bf16(float x, uint32_t& hi, uint32_t& lo) {
-    hi = bf16_bits(x);
-    const float r = x - bf16_value(hi);
-    lo = (r == r && __builtin_fabsf(r) != __builtin_inff()) ? bf16_bits(r) : 0u;
+// hi and lo bf16 halves of two FP32 values, packed two per 32-bit word
+// (hardware round-to-nearest-even conversion).  lo = 0 where the residual is
+// NaN (an infinite input), so infinities propagate through hi * hi alone.
+__device__ __forceinline__ void split_bf16x2(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+    const f32x2 x = {x0, x1};
+    const bf16x2 h = __builtin_convertvector(x, bf16x2);
+    f32x2 r = x - __builtin_convertvector(h, f32x2);
+    r[0] = r[0] == r[0] ? r[0] : 0.f;
+    r[1] = r[1] == r[1] ? r[1] : 0.f;
+    const bf16x2 l = __builtin_convertvector(r, bf16x2);
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, l);
 }
 
 // Pack stage of one operand for the split mode: each thread gathers pairs of
@@ -763,12 +806,11 @@ struct PackPair {
 #pragma unroll
         for (int i = 0; i < EP; ++i) {
             const int q = t + NTHR * i;
-            uint32_t h0, l0, h1, l1;
-            split_bf16(r0[i], h0, l0);
-            split_bf16(r1[i], h1, l1);
+            uint32_t h, l;
+            split_bf16x2(r0[i], r1[i], h, l);
             const int w = (ridx(q) * KTP + 2 * pidx(q)) >> 1;
-            hi[w] = h0 | (h1 << 16);
-            lo[w] = l0 | (l1 << 16);
+            hi[w] = h;
+            lo[w] = l;
         }
     }
 };
@@ -965,6 +1007,8 @@ static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, co
     a.spanY = p.swapped ? p.spanA : p.spanB;
     a.alpha = (T)alpha;
     a.beta = (T)beta;
+    a.kregX = p.k_blocks_regular_x == (int64_t)p.kbsX.size();
+    a.kregY = p.k_blocks_regular_y == (int64_t)p.kbsY.size();
     if (p.m == 0 || p.n == 0) return TC_OK;
     if (p.k_empty || p.k == 0 || alpha == 0.0) {
         int64_t total = p.m * p.n;
@@ -1044,6 +1088,8 @@ __global__ __launch_bounds__(WM* WN * 64) void batch_kernel(const BatchItemDev* 
         a.spanY = it.spanY;
         a.alpha = (T)it.alpha;
         a.beta = (T)it.beta;
+        a.kregX = it.kregX;
+        a.kregY = it.kregY;
         const int64_t tile = w - it.first_item;
         if (it.x_lanes_m) {
             if (it.y_lanes_n) TTT::run(a, tile, smem);

@@ -32,6 +32,7 @@ struct BatchItemDev {
     int64_t spanX, spanY;
     double alpha, beta;
     int32_t x_lanes_m, y_lanes_n;
+    int32_t kregX, kregY;  // 1: every k block of X (Y) has a nonzero block stride
 };
 
 // Launch the persistent batched kernel of tile configuration `tile` over
