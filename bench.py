@@ -233,17 +233,9 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only (no secondary workloads)")
     ap.add_argument("--tile", type=int, default=None, help="force a tile configuration")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="run only a plain 1 GiB device copy (reference for HBM byte counters)")
+                    help="first run a plain 1 GiB device copy three times (the reference for HBM byte "
+                         "counters, taken in the same process as the contraction)")
     args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 3}))
-        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -254,6 +246,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 8, "copy_bytes_written": y.numel() * 8, "launches": 3}),
+              file=sys.stderr, flush=True)
+        del x, y
     p = inputs.cfg2()
     m, n, k = p.mnk()
     flops = 2.0 * m * n * k

@@ -716,21 +716,19 @@ struct TilePinwheel8 {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
+// round-to-nearest-even FP32 -> bf16 bits; NaN stays NaN
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+    const uint32_t u = __builtin_bit_cast(uint32_t, x);
+    if (x != x) return 0x7fc0u;
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_value(uint32_t h) { return __builtin_bit_cast(float, h << 16); }
 
-// hi and lo bf16 halves of two FP32 values, packed two per 32-bit word
-// (hardware round-to-nearest-even conversion).  lo = 0 where the residual is
-// NaN (an infinite input), so infinities propagate through hi * hi alone.
-__device__ __forceinline__ void split_bf16x2(float x0, float x1, uint32_t& hi, uint32_t& lo) {
-    const f32x2 x = {x0, x1};
-    const bf16x2 h = __builtin_convertvector(x, bf16x2);
-    f32x2 r = x - __builtin_convertvector(h, f32x2);
-    r[0] = r[0] == r[0] ? r[0] : 0.f;
-    r[1] = r[1] == r[1] ? r[1] : 0.f;
-    const bf16x2 l = __builtin_convertvector(r, bf16x2);
-    hi = __builtin_bit_cast(uint32_t, h);
-    lo = __builtin_bit_cast(uint32_t, l);
+// hi and lo halves of x (lo = 0 when x is not finite)
+__device__ __forceinline__ void split_bf16(float x, uint32_t& hi, uint32_t& lo) {
+    hi = bf16_bits(x);
+    const float r = x - bf16_value(hi);
+    lo = (r == r && __builtin_fabsf(r) != __builtin_inff()) ? bf16_bits(r) : 0u;
 }
 
 // Pack stage of one operand for the split mode: each thread gathers pairs of
@@ -806,11 +804,12 @@ struct PackPair {
 #pragma unroll
         for (int i = 0; i < EP; ++i) {
             const int q = t + NTHR * i;
-            uint32_t h, l;
-            split_bf16x2(r0[i], r1[i], h, l);
+            uint32_t h0, l0, h1, l1;
+            split_bf16(r0[i], h0, l0);
+            split_bf16(r1[i], h1, l1);
             const int w = (ridx(q) * KTP + 2 * pidx(q)) >> 1;
-            hi[w] = h;
-            lo[w] = l;
+            hi[w] = h0 | (h1 << 16);
+            lo[w] = l0 | (l1 << 16);
         }
     }
 };
@@ -1034,7 +1033,7 @@ static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, co
 #define TC_CASE(id, MT, NT, KT, WM, WN, L) \
     case id:                               \
         return launch_tile<T, OffT, MT, NT, KT, WM, WN, L>(a, xm, yn, s);
-    if (p.dtype == TC_F64) {
+    if constexpr (sizeof(T) == 8) {
         switch (p.tile) { TC_TILES_F64(TC_CASE) }
     } else {
         switch (p.tile) { TC_TILES_F32(TC_CASE) }
@@ -1138,7 +1137,8 @@ static int batch_dispatch(int dtype, int tile, bool launch, const BatchItemDev* 
     case id:                                                                                              \
         return launch ? BatchLaunch<T, OffT, MT, NT, KT, WM, WN, L>::launch(items, count, total, grid, s) \
                       : BatchLaunch<T, OffT, MT, NT, KT, WM, WN, L>::grid(total);
-    if (dtype == TC_F64) {
+    (void)dtype;  // the storage type T fixes the tile table
+    if constexpr (sizeof(T) == 8) {
         switch (tile) { TC_TILES_F64(TC_BCASE) }
     } else {
         switch (tile) { TC_TILES_F32(TC_BCASE) }
