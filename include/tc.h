@@ -158,36 +158,43 @@ int tc_plan_autotune(tc_plan* plan, const void* A, const void* B, void* C_scratc
                      double* best_ms);
 
 /*
- * Batched contractions in ONE persistent kernel launch (many independent
+ * Batched contractions in persistent kernel launches (many independent
  * contractions of uneven sizes and index permutations).  tc_batch_create
  * plans every problem (all with the same dtype and mode), uploads one
  * descriptor table plus all offset vectors to the current device
  * (synchronous), and binds the given device pointers and scalars: problem i
  * is C_i := alpha[i] * A_i . B_i + beta[i] * C_i with plans[i].  The plans
- * are only read during the call.  tc_batch_execute then issues a single
- * launch whose workgroups walk a flattened list of (problem, tile) work items;
- * it makes no allocation and no host-device copy, so it may be recorded in a
- * hipGraph and replayed.  C_i must not overlap each other.
+ * are only read during the call.  tc_batch_execute then issues one persistent
+ * launch per tile class present (see tc_batch_info) whose workgroups walk a
+ * flattened list of (problem, tile) work items; it makes no allocation and no
+ * host-device copy, so it may be recorded in a hipGraph and replayed.  C_i
+ * must not overlap each other.
  */
 int tc_batch_create(tc_batch** batch, int count, const tc_plan* const* plans, const double* alpha,
                     const void* const* A, const void* const* B, const double* beta, void* const* C);
 int tc_batch_execute(const tc_batch* batch, void* stream);
 int tc_batch_destroy(tc_batch* batch);
-/* Work-item count, the tile configuration and the persistent grid size of
- * the batch launch.  Problems are laid out in decreasing order of k (the cost
- * of one tile) so that the workgroups' static stride over the work list is
- * balanced.  One tile configuration serves the whole batch; all regular
+/* Work-item count, the tile configuration (-1: per-problem classes) and the
+ * largest persistent grid of the batch.  By default every problem runs with
+ * the regular tile configuration the planner's cost model picks for it alone;
+ * problems of one class share one persistent launch (so a batch issues at
+ * most one launch per regular configuration, the class with the most work
+ * first), laid out in decreasing order of k (the cost of one tile) so that
+ * the workgroups' static stride over the work list is balanced.  All regular
  * configurations of a dtype share KT, so each output element is summed in
- * the same order as by tc_plan_execute with a regular tile (bitwise equal). */
+ * the same order as by tc_plan_execute with any regular tile (bitwise
+ * equal). */
 int tc_batch_info(const tc_batch* batch, int64_t* work_items, int* tile, int* grid);
-/* Change the batch's tile configuration (regular layouts only); re-uploads
- * the work table (synchronous, not during capture). */
+/* Set one tile configuration for the whole batch (regular layouts only), or
+ * -1 for per-problem classes; re-uploads the work table (synchronous, not
+ * during capture). */
 int tc_batch_set_tile(tc_batch* batch, int tile);
-/* Autotuner for batches: times the whole batch launch (reps runs after one
- * warm-up, hipEvent timing on `stream`) under every regular tile
- * configuration and keeps the fastest.  Runs the batch (1 + reps) times per
- * configuration, so outputs with beta != 0 are updated repeatedly: tune on
- * scratch outputs.  Synchronises `stream`.  *best_ms may be NULL. */
+/* Autotuner for batches: times the whole batch (reps runs after one warm-up,
+ * hipEvent timing on `stream`) with per-problem classes and under every
+ * single regular tile configuration, and keeps the fastest.  Runs the batch
+ * (1 + reps) times per candidate, so outputs with beta != 0 are updated
+ * repeatedly: tune on scratch outputs.  Synchronises `stream`.  *best_ms may
+ * be NULL. */
 int tc_batch_autotune(tc_batch* batch, int reps, void* stream, double* best_ms);
 
 /*

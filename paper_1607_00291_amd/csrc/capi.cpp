@@ -21,13 +21,21 @@ struct tc_plan {
 };
 
 struct tc_batch {
-    int dtype = 0, mode = 0, tile = 0, count = 0, device = 0, grid = 0;
+    // tile < 0: every problem runs with its own tile class (one persistent
+    // launch per class present); else one class for the whole batch
+    int dtype = 0, mode = 0, tile = -1, count = 0, device = 0, grid = 0;
     bool off64 = false;
     int64_t total_items = 0;
-    std::vector<tc::BatchItemDev> host;  // per problem, in launch order (device pointers filled)
+    std::vector<tc::BatchItemDev> host;  // per problem (device pointers filled)
+    std::vector<int> best;               // per problem: its own regular tile class
     std::vector<int> order;              // problem index of each table entry
-    void* table = nullptr;    // device BatchItemDev[count]
-    void* vectors = nullptr;  // device arena holding every problem's vectors
+    struct Segment {
+        int tile, first, count, grid;
+        int64_t items;
+    };
+    std::vector<Segment> segs;  // launches, in issue order
+    void* table = nullptr;      // device BatchItemDev[count]
+    void* vectors = nullptr;    // device arena holding every problem's vectors
 };
 
 namespace tc {
@@ -424,28 +432,58 @@ int tc_contract(double alpha, const void* A, int ndim_A, const int64_t* lens_A, 
 
 namespace tc {
 
-// Work-item counts and prefix sums of a batch for its current tile, then the
-// table upload.  Problems are ordered by decreasing k (the cost of one tile),
-// so that the static stride assignment of the persistent kernel is balanced.
+// Work-item counts and prefix sums of a batch, then the table upload.  The
+// table is grouped by tile class (one persistent launch per class, the class
+// with the most work first); inside a class problems are ordered by
+// decreasing k (the cost of one tile), so that the static stride assignment
+// of the persistent kernel is balanced.
 static int batch_layout(tc_batch* b) {
-    const TileCfg& t = tile_table(b->dtype, b->mode)[b->tile];
-    std::vector<int> idx(b->host.size());
-    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
-    std::vector<BatchItemDev> items = b->host;
-    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return items[x].k > items[y].k; });
+    const TileCfg* tab = tile_table(b->dtype, b->mode);
+    const std::vector<BatchItemDev>& items = b->host;
+    const size_t n = items.size();
+    std::vector<int> cls(n);
+    for (size_t i = 0; i < n; ++i) cls[i] = b->tile >= 0 ? b->tile : b->best[i];
+    const int nt = tile_count(b->dtype, b->mode);
+    std::vector<double> work(nt, 0.0);
+    for (size_t i = 0; i < n; ++i) {
+        const TileCfg& t = tab[cls[i]];
+        work[cls[i]] += (double)((items[i].m + t.MT - 1) / t.MT) * (double)((items[i].n + t.NT - 1) / t.NT) *
+                        t.MT * t.NT * (double)std::max<int64_t>(items[i].k, 1);
+    }
+    std::vector<int> rank(nt);
+    for (int c = 0; c < nt; ++c) rank[c] = c;
+    std::stable_sort(rank.begin(), rank.end(), [&](int x, int y) { return work[x] > work[y]; });
+    std::vector<int> pos(nt);
+    for (int r = 0; r < nt; ++r) pos[rank[r]] = r;
+    std::vector<int> idx(n);
+    for (size_t i = 0; i < n; ++i) idx[i] = (int)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+        if (cls[x] != cls[y]) return pos[cls[x]] < pos[cls[y]];
+        return items[x].k > items[y].k;
+    });
     std::vector<BatchItemDev> table;
-    table.reserve(items.size());
+    table.reserve(n);
+    b->segs.clear();
+    b->total_items = 0;
     int64_t first = 0;
-    for (int i : idx) {
+    for (size_t e = 0; e < n; ++e) {
+        const int i = idx[e];
+        const TileCfg& t = tab[cls[i]];
+        if (b->segs.empty() || b->segs.back().tile != cls[i]) {
+            b->segs.push_back({cls[i], (int)e, 0, 0, 0});
+            first = 0;
+        }
         BatchItemDev it = items[i];
         it.tiles_m = (it.m + t.MT - 1) / t.MT;
         it.tiles_n = (it.n + t.NT - 1) / t.NT;
         it.first_item = first;
         first += it.tiles_m * it.tiles_n;
+        b->segs.back().count++;
+        b->segs.back().items = first;
+        b->total_items += it.tiles_m * it.tiles_n;
         table.push_back(it);
     }
     b->order = idx;
-    b->total_items = first;
     if (!b->table) {
         hipError_t e = hipMalloc(&b->table, std::max<size_t>(table.size(), 1) * sizeof(BatchItemDev));
         if (e != hipSuccess) {
@@ -458,10 +496,14 @@ static int batch_layout(tc_batch* b) {
         hipError_t e = hipMemcpy(b->table, table.data(), table.size() * sizeof(BatchItemDev), hipMemcpyHostToDevice);
         if (e != hipSuccess) return hipfail(e, "hipMemcpy of the batch table");
     }
-    b->grid = batch_grid(b->dtype, b->mode, b->tile, b->off64, b->total_items);
-    if (b->total_items > 0 && b->grid <= 0) {
-        set_error("could not size the persistent grid");
-        return TC_ERR_HIP;
+    b->grid = 0;
+    for (auto& sg : b->segs) {
+        sg.grid = sg.items > 0 ? batch_grid(b->dtype, b->mode, sg.tile, b->off64, sg.items) : 0;
+        if (sg.items > 0 && sg.grid <= 0) {
+            set_error("could not size the persistent grid");
+            return TC_ERR_HIP;
+        }
+        b->grid = std::max(b->grid, sg.grid);
     }
     return TC_OK;
 }
@@ -578,6 +620,7 @@ static int batch_create(tc_batch** out, int count, const tc_plan* const* plans, 
         it.kregX = p.k_blocks_regular_x == (int64_t)p.kbsX.size();
         it.kregY = p.k_blocks_regular_y == (int64_t)p.kbsY.size();
         b->host.push_back(it);
+        b->best.push_back(choose_tile(p, true));
     }
     if (total) {
         hipError_t e = hipMemcpy(b->vectors, host.data(), total * w, hipMemcpyHostToDevice);
@@ -586,7 +629,7 @@ static int batch_create(tc_batch** out, int count, const tc_plan* const* plans, 
             return hipfail(e, "hipMemcpy of the batch vectors");
         }
     }
-    b->tile = 1 < tile_count(dtype, mode) ? 1 : 0;  // 64 x 64 until tuned
+    b->tile = -1;  // every problem with its own tile class until tuned
     int st = batch_layout(b.get());
     if (st) {
         tc_batch_destroy(b.release());
@@ -625,8 +668,14 @@ int tc_batch_execute(const tc_batch* batch, void* stream) {
         set_error("batch executed on a device other than the one it was created on");
         return TC_ERR_ARG;
     }
-    return launch_batch(batch->dtype, batch->mode, batch->tile, batch->off64, (const BatchItemDev*)batch->table,
-                        (int)batch->host.size(), batch->total_items, batch->grid, (hipStream_t)stream);
+    for (const auto& sg : batch->segs) {
+        if (sg.items == 0) continue;
+        int st = launch_batch(batch->dtype, batch->mode, sg.tile, batch->off64,
+                              (const BatchItemDev*)batch->table + sg.first, sg.count, sg.items, sg.grid,
+                              (hipStream_t)stream);
+        if (st) return st;
+    }
+    return TC_OK;
 }
 
 int tc_batch_set_tile(tc_batch* batch, int tile) {
@@ -634,8 +683,8 @@ int tc_batch_set_tile(tc_batch* batch, int tile) {
         set_error("batch is NULL");
         return TC_ERR_NULL;
     }
-    if (tile < 0 || tile >= tile_count(batch->dtype, batch->mode) ||
-        tile_table(batch->dtype, batch->mode)[tile].layout != 0) {
+    if (tile < -1 || tile >= tile_count(batch->dtype, batch->mode) ||
+        (tile >= 0 && tile_table(batch->dtype, batch->mode)[tile].layout != 0)) {
         set_error("not a regular tile configuration of this dtype/mode");
         return TC_ERR_ARG;
     }
@@ -666,8 +715,8 @@ int tc_batch_autotune(tc_batch* batch, int reps, void* stream, double* best_ms) 
     int best = batch->tile, st = TC_OK;
     float best_t = 1e30f;
     const int nt = tile_count(batch->dtype, batch->mode);
-    for (int t = 0; t < nt && st == TC_OK; ++t) {
-        if (tile_table(batch->dtype, batch->mode)[t].layout != 0) continue;
+    for (int t = -1; t < nt && st == TC_OK; ++t) {  // -1: every problem with its own class
+        if (t >= 0 && tile_table(batch->dtype, batch->mode)[t].layout != 0) continue;
         if ((st = tc_batch_set_tile(batch, t))) break;
         if ((st = tc_batch_execute(batch, s))) break;  // warm-up
         hipEventRecord(e0, s);

@@ -251,13 +251,16 @@ struct PackOp {
 
     // Global gather of k block kb.  A valid block stride (Sec. 6.2) replaces
     // the per-element scatter-vector reads along k; the choice is uniform.
+    // REG = 1: every block of this operand is known to have one (no per-k
+    // offset reads compiled in); REG = -1: decided per block.
+    template <int REG = -1>
     __device__ __forceinline__ void load(const T* base, int64_t span, const OffT* kvec, const OffT* kbs, OffT kb, OffT K,
                                          int t) {
         const OffT k0 = kb * KT;
         const OffT sk = uniform(kbs[kb]);
         OffT ko[E];
         OffT kbase = 0;
-        if (sk) {
+        if (REG == 1 || sk) {
             kbase = uniform(kvec[k0]);
 #pragma unroll
             for (int i = 0; i < E; ++i) ko[i] = (OffT)kidx(t + NTHR * i) * sk;
@@ -309,9 +312,10 @@ struct Pack {
         px.init(a.rX, m0, a.m, t);
         py.init(a.cY, n0, a.n, t);
     }
+    template <int REG = -1>
     __device__ __forceinline__ void load(const KArgs<T, OffT>& a, OffT kb, int t) {
-        px.load(a.X, a.spanX, a.cX, a.kbsX, kb, a.k, t);
-        py.load(a.Y, a.spanY, a.rY, a.kbsY, kb, a.k, t);
+        px.template load<REG>(a.X, a.spanX, a.cX, a.kbsX, kb, a.k, t);
+        py.template load<REG>(a.Y, a.spanY, a.rY, a.kbsY, kb, a.k, t);
     }
     __device__ __forceinline__ void store(T* smem, int buf, int t) const {
         px.store(smem + buf * XS, t);
@@ -430,14 +434,17 @@ struct TileRegular {
                 for (int r = 0; r < 4; ++r) acc[i][j][r] = T(0);
 
         const OffT nkb = (a.k + KT - 1) / KT;
-        if (nkb > 0) {
-            pk.load(a, 0, tid);
+        // The gathers of stage kb + 1 and their LDS store run with no branch
+        // around them: past the last stage they re-read the last block and
+        // fill the LDS buffer that no stage reads any more.
+        auto pipeline = [&](auto reg) {
+            constexpr int RG = decltype(reg)::value;
+            pk.template load<RG>(a, 0, tid);
             pk.store(smem, 0, tid);
             __syncthreads();
             for (OffT kb = 0; kb < nkb; ++kb) {
                 const int buf = (int)(kb & 1);
-                const bool more = kb + 1 < nkb;
-                if (more) pk.load(a, kb + 1, tid);
+                pk.template load<RG>(a, kb + 1 < nkb ? kb + 1 : kb, tid);
                 const T* bx = smem + buf * P::XS + wm * WTM;
                 const T* by = smem + 2 * P::XS + buf * P::YS + wn * WTN;
 #pragma unroll
@@ -454,9 +461,13 @@ struct TileRegular {
 #pragma unroll
                         for (int j = 0; j < FN; ++j) M::run(fa[i], fb[j], acc[i][j]);
                 }
-                if (more) pk.store(smem, buf ^ 1, tid);
+                pk.store(smem, buf ^ 1, tid);
                 __syncthreads();
             }
+        };
+        if (nkb > 0) {
+            if (a.kregX && a.kregY) pipeline(std::integral_constant<int, 1>());
+            else pipeline(std::integral_constant<int, -1>());
         }
         // alpha/beta scatter-store through rscat_C / cscat_C (Sec. 6.1)
 #pragma unroll

@@ -315,24 +315,31 @@ void set_plan_tile(Plan* p, int tile) {
     for (auto& d : p->dev) d.bytes = 0;  // device copies are stale (freed lazily)
 }
 
-// Wave-quantisation-aware choice: estimated time = rounds of tiles over the
-// chip's 256 CUs times the work of one tile, plus a per-tile overhead; larger
-// tiles win ties (better reuse of A and B slivers).
-int choose_tile(const Plan& p) {
+// Cost model over the compiled tiles: the per-CU compute time of the tile
+// rounds (wave quantisation over the chip's 256 CUs, with up to `occ`
+// workgroups resident per CU and the measured rate for that residency),
+// bounded below by the time to stream every tile's A and B slivers from the
+// caches (small tiles re-read the operands many times).  Earlier tiles win
+// ties.
+int choose_tile(const Plan& p, bool regular_only) {
     const TileCfg* tab = tile_table(p.dtype, p.mode);
-    int nt = tile_count(p.dtype, p.mode);
-    const double cus = 256.0;
+    const TileRate* rate = rate_table(p.dtype, p.mode);
+    const int nt = tile_count(p.dtype, p.mode);
+    const double cus = 256.0, cache_bw = 4e12;
+    const double esize = p.dtype == TC_F64 ? 8.0 : 4.0;
+    const double k = (double)std::max<int64_t>(p.k, 1);
     int best = 0;
     double best_t = 1e300;
     for (int i = 0; i < nt; ++i) {
         const TileCfg& t = tab[i];
-        double tm = (double)((p.m + t.MT - 1) / t.MT), tn = (double)((p.n + t.NT - 1) / t.NT);
-        double tiles = tm * tn;
-        // smaller tiles have lower operand reuse: charge the bytes moved per flop
-        double work = (double)t.MT * t.NT * (double)std::max<int64_t>(p.k, 1);
-        double reuse_penalty = 1.0 + 24.0 / t.MT + 24.0 / t.NT;
-        double rounds = std::ceil(tiles / cus);
-        double time = rounds * work * reuse_penalty + tiles * 2000.0 / cus;
+        if (regular_only && t.layout != 0) continue;
+        const double tiles = (double)((p.m + t.MT - 1) / t.MT) * (double)((p.n + t.NT - 1) / t.NT);
+        const double w = std::min((double)rate[i].occ, std::ceil(tiles / cus));
+        const double rounds = std::ceil(tiles / (cus * w));
+        const double r = (w >= 2.0 ? rate[i].r2 : rate[i].r1) * 1e12 / cus;  // flop/s of one CU
+        const double compute = rounds * w * 2.0 * t.MT * t.NT * k / r;
+        const double stream = tiles * (double)(t.MT + t.NT) * k * esize / cache_bw;
+        const double time = std::max(compute, stream);
         if (time < best_t * 0.999) {
             best_t = time;
             best = i;

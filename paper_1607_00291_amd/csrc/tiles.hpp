@@ -46,6 +46,22 @@ static const TileCfg kTilesF32[] = {TC_TILES_F32(TC_TILE_ENTRY)};
 static const TileCfg kTilesBF16x3[] = {TC_TILES_BF16X3(TC_TILE_ENTRY)};
 #undef TC_TILE_ENTRY
 
+// Measured throughput of each tile configuration on MI355X (TFLOP/s, dense
+// column-major contractions of shapes 4096^2 x 1024, 2304^3, 2048^2 x 1024
+// and 1024^2 x 4096): r1 with one workgroup per compute unit, r2 with two or
+// more resident, occ the workgroups that fit on one compute unit at once.
+// The planner's cost model (choose_tile) is built on these figures.
+struct TileRate {
+    double r1, r2;
+    int occ;
+};
+static const TileRate kRatesF64[] = {{31, 31, 2}, {25, 46, 2}, {35, 52, 2}, {40.6, 40.6, 1}, {51.4, 51.4, 1}};
+static const TileRate kRatesF32[] = {{50, 54, 2}, {41, 86, 2}, {58, 94, 2}, {65, 96, 2}, {94, 94, 1}};
+static const TileRate kRatesBF16x3[] = {{45, 50, 2}, {38, 105, 2}, {59, 104, 2}, {76, 145, 2}};
+static_assert(sizeof(kRatesF64) / sizeof(TileRate) == sizeof(kTilesF64) / sizeof(TileCfg), "one rate per tile");
+static_assert(sizeof(kRatesF32) / sizeof(TileRate) == sizeof(kTilesF32) / sizeof(TileCfg), "one rate per tile");
+static_assert(sizeof(kRatesBF16x3) / sizeof(TileRate) == sizeof(kTilesBF16x3) / sizeof(TileCfg), "one rate per tile");
+
 inline int tile_count(int dtype, int mode) {
     if (dtype == 0 && mode == 0) return (int)(sizeof(kTilesF64) / sizeof(TileCfg));
     if (dtype == 1 && mode == 0) return (int)(sizeof(kTilesF32) / sizeof(TileCfg));
@@ -57,6 +73,13 @@ inline const TileCfg* tile_table(int dtype, int mode) {
     if (dtype == 0 && mode == 0) return kTilesF64;
     if (dtype == 1 && mode == 0) return kTilesF32;
     if (dtype == 1 && mode == 1) return kTilesBF16x3;
+    return nullptr;
+}
+
+inline const TileRate* rate_table(int dtype, int mode) {
+    if (dtype == 0 && mode == 0) return kRatesF64;
+    if (dtype == 1 && mode == 0) return kRatesF32;
+    if (dtype == 1 && mode == 1) return kRatesBF16x3;
     return nullptr;
 }
 

@@ -212,8 +212,10 @@ class Batch:
     ``problems`` is a list of (A, idx_A, B, idx_B, C, idx_C, alpha, beta) with
     torch tensors on the current device, all of one dtype.  The tensors are
     bound at construction (their pointers go into the device work table), so
-    they must stay alive while the batch is used.  ``execute`` issues a single
-    kernel launch and may be recorded in a CUDA/HIP graph.
+    they must stay alive while the batch is used.  ``execute`` issues one
+    persistent launch per tile class present (``tile`` = -1: every problem with
+    the class the planner picks for it; else one class for all) and may be
+    recorded in a HIP graph.
     """
 
     def __init__(self, problems, mode="native"):

@@ -28,10 +28,12 @@ def test_batched_equals_sequential_and_oracle(oracle_mod, dtype):
     info = batch.info()
     print(f"case batched dtype={dtype.__name__} {info}", flush=True)
     batch.execute()
-    # sequential launches with the batch's tile configuration
+    assert info["tile"] == -1  # default: every problem with its own tile class
+    # sequential launches with a regular tile: every regular configuration
+    # sums each output in the same order, so any of them matches bitwise
     for p, (A, B, _), Cs in zip(probs, dev, seq_out):
         plan = tc.Plan.for_tensors(A, p.idx_A, B, p.idx_B, Cs, p.idx_C)
-        plan.tile = info["tile"]
+        plan.tile = 1
         plan.execute(A, B, Cs, p.alpha, p.beta)
         plan.close()
     torch.cuda.synchronize()
@@ -53,10 +55,9 @@ def test_batched_every_tile_and_graph_replay(oracle_mod):
     dev = [(to_dev(p.A), to_dev(p.B), to_dev(p.C)) for p in probs]
     batch = tc.Batch([(A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 0.0) for p, (A, B, C) in zip(probs, dev)])
     ref = None
-    for t in range(tc.tile_count(tc.TC_F64)):
-        MT, NT, KT, waves = tc.tile_info(tc.TC_F64, tc.TC_NATIVE, t)
-        if MT == 144:  # the pinwheel layout is single-problem only
-            continue
+    for t in [-1] + list(range(tc.tile_count(tc.TC_F64))):
+        if t >= 0 and tc.tile_info(tc.TC_F64, tc.TC_NATIVE, t)[0] == 144:
+            continue  # the pinwheel layout is single-problem only
         batch.tile = t
         for _, _, C in dev:
             C.zero_()
@@ -69,9 +70,10 @@ def test_batched_every_tile_and_graph_replay(oracle_mod):
         else:  # every regular tile sums in the same order: bitwise equal
             for a, b in zip(ref, outs):
                 assert np.array_equal(a, b)
-    # graph capture of the single persistent launch, replayed with eager work
-    # in between; every replay must reproduce the eager result
-    batch.tile = 1
+    # graph capture of the persistent launches (one per tile class present),
+    # replayed with eager work in between; every replay must reproduce the
+    # eager result
+    batch.tile = -1
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -99,7 +101,7 @@ def test_autotune_batch_and_plan():
     dev = [(to_dev(p.A), to_dev(p.B), to_dev(p.C)) for p in probs]
     batch = tc.Batch([(A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 0.0) for p, (A, B, C) in zip(probs, dev)])
     tile, ms = batch.autotune(reps=2)
-    assert ms > 0 and 0 <= tile < tc.tile_count(tc.TC_F64)
+    assert ms > 0 and -1 <= tile < tc.tile_count(tc.TC_F64)
     p = probs[-1]
     A, B, C = dev[-1]
     plan = tc.Plan.for_tensors(A, p.idx_A, B, p.idx_B, C, p.idx_C)
