@@ -186,8 +186,54 @@ def secondary(tc, inputs, steps, warmup, quick):
     del A, B, C
     if not quick:
         out["batched_512_fp64"] = batched(tc, inputs, steps, warmup)
+        out["random_sweep_fp64"] = sweep(tc, inputs, max(steps // 2, 5), 2)
     torch.cuda.empty_cache()
     return out
+
+
+def sweep(tc, inputs, steps, warmup, square=(512, 1024, 2048, 4096), rankk=(8, 32, 128, 512), big=4096, seeds=3):
+    """Random contractions in the manner of the paper's generator (Sec. 9.2),
+    FP64: square shapes m ~ n ~ k and rank-k shapes m ~ n ~ 4096 with small k,
+    each timed against a plain column-major GEMM of the same m, n, k run by
+    the same library (the transpose-free path's cost of arbitrary layouts).
+    Also reports the fraction of C tiles and k blocks with a constant block
+    stride (the fast-path share, Sec. 6.2)."""
+    import torch
+    rows = []
+    cases = [("square", t, t, t) for t in square] + [("rank-k", big, big, kk) for kk in rankk]
+    for kind, m0, n0, k0 in cases:
+        rates, gemm_rates, fast_c, fast_k = [], [], [], []
+        for sd in range(seeds):
+            p = inputs.sweep_problem(1000 * sd + m0 + k0, m0, n0, k0)
+            m, n, k = p.mnk()
+            A, B, C = dev(p.A), dev(p.B), dev(p.C)
+            plan, run = plan_runner(tc, A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 0.0)
+            d = plan.describe()
+            ms = time_calls(run, steps, warmup)
+            plan.close()
+            del A, B, C
+            A2 = torch.zeros(k, m, dtype=torch.float64, device="cuda").t()
+            B2 = torch.zeros(n, k, dtype=torch.float64, device="cuda").t()
+            C2 = torch.zeros(n, m, dtype=torch.float64, device="cuda").t()
+            A2.normal_()
+            B2.normal_()
+            plan, run = plan_runner(tc, A2, "ik", B2, "kj", C2, "ij", 1.0, 0.0)
+            ms_g = time_calls(run, steps, warmup)
+            plan.close()
+            del A2, B2, C2
+            rates.append(2.0 * m * n * k / ms / 1e6)
+            gemm_rates.append(2.0 * m * n * k / ms_g / 1e6)
+            fast_c.append(d["c_tiles_regular"] / max(d["tiles_m"] * d["tiles_n"], 1))
+            kb = max(d["k_blocks"], 1)
+            fast_k.append(min(d["k_blocks_regular_x"], d["k_blocks_regular_y"]) / kb)
+        rows.append({"kind": kind, "target_mnk": [m0, n0, k0], "instances": seeds,
+                     "gflops_mean": round(float(np.mean(rates)), 1), "gflops_min": round(float(np.min(rates)), 1),
+                     "gemm_gflops_mean": round(float(np.mean(gemm_rates)), 1),
+                     "ratio_to_gemm": round(float(np.mean(np.array(rates) / np.array(gemm_rates))), 3),
+                     "fast_c_tiles": round(float(np.mean(fast_c)), 3),
+                     "fast_k_blocks": round(float(np.mean(fast_k)), 3)})
+    torch.cuda.empty_cache()
+    return rows
 
 
 def batched(tc, inputs, steps, warmup):

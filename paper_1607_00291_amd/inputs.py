@@ -188,3 +188,47 @@ def random_problem(seed, n_i=2, n_j=2, n_p=2, lo=1, hi=7, beta=0.0, alpha=1.0, i
     B = mk(ib)
     C = mk(ic) if beta != 0.0 else colmajor(shape_of(ic, ext), fill=0.0)
     return Problem(ia, ib, ic, A, B, C, alpha, beta, f"random[{seed}]", ext)
+
+
+def split_extent(rng, target, dims):
+    """``dims`` extents (each >= 2) whose product is close to ``target``: the
+    log of the target cut at dims - 1 uniform random points, the last extent
+    then absorbing the rounding of the others."""
+    if dims <= 1:
+        return [max(int(target), 1)]
+    cuts = np.sort(rng.random(dims - 1))
+    parts = np.diff(np.concatenate([[0.0], cuts, [1.0]])) * np.log(max(target, 1))
+    lens = [max(int(round(float(np.exp(x)))), 2) for x in parts[:-1]]
+    lens.append(max(int(round(target / float(np.prod(lens)))), 2))
+    return lens
+
+
+def sweep_instance(rng, m, n, k):
+    """A contraction whose matrix view is about m x n x k, in the manner of
+    the paper's random-contraction generator (Sec. 9.2): each of the bundles
+    I, J and P gets one to three labels whose extents multiply to about m, n
+    and k, and every operand's storage order is an independent random
+    permutation of its labels."""
+    labels = iter("abcdefghijklmnopqrstuvwxyz")
+    ext, bundles = {}, []
+    for target in (m, n, k):
+        lens = split_extent(rng, target, int(rng.integers(1, 4)))
+        labs = [next(labels) for _ in lens]
+        ext.update(zip(labs, lens))
+        bundles.append(labs)
+    I, J, P = bundles
+    ic = "".join(rng.permutation(I + J))
+    ia = "".join(rng.permutation(I + P))
+    ib = "".join(rng.permutation(P + J))
+    return ext, ia, ib, ic
+
+
+def sweep_problem(seed, m, n, k, dtype=np.float64):
+    """Seeded sweep instance with U[-1,1] operands (A then B), C = 0, alpha 1,
+    beta 0."""
+    rng = np.random.default_rng(seed)
+    ext, ia, ib, ic = sweep_instance(rng, m, n, k)
+    A = _uniform(rng, ia, ext).astype(dtype, order="F")
+    B = _uniform(rng, ib, ext).astype(dtype, order="F")
+    C = colmajor(shape_of(ic, ext), dtype=dtype, fill=0.0)
+    return Problem(ia, ib, ic, A, B, C, 1.0, 0.0, f"sweep[{seed}:{m}x{n}x{k}]", ext)

@@ -60,6 +60,17 @@ def test_random_small_fp64(oracle_mod, seed):
     check_fp64(oracle_mod, p, gpu_result(p))
 
 
+@pytest.mark.parametrize("shape", [(300, 200, 50), (160, 170, 9), (400, 64, 200), (97, 301, 33)])
+def test_sweep_instances(oracle_mod, shape):
+    """Random-contraction sweep instances (one to three labels per bundle,
+    random storage orders), as timed by the bench sweep, at sizes the oracle
+    finishes quickly."""
+    for sd in range(3):
+        p = inputs.sweep_problem(77 + sd, *shape)
+        print(f"case sweep {shape} seed={77 + sd} {p.idx_A},{p.idx_B}->{p.idx_C} {p.extents}", flush=True)
+        check_fp64(oracle_mod, p, gpu_result(p))
+
+
 @pytest.mark.parametrize("ext", [1, 3, 17, 97])
 def test_ragged_extents_every_tile(oracle_mod, ext):
     """Extents that leave ragged tiles in m, n and k, under every tile config."""
