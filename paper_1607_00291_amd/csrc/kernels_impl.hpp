@@ -654,14 +654,29 @@ struct TilePinwheel8 {
                 const int kr0 = lane >> 4;
                 // the centre fragment's k-steps go round-robin over the waves
                 const int cs = (wave - (int)((kb * (KT / 4)) & 7)) & 7;  // this wave's centre k-step, if < KT/4
-                if (cs < KT / 4) {
-                    ca = M::load_a(bx + (4 * cs + kr0) * LDX + 64, lane);
-                    cb = M::load_b(by + (4 * cs + kr0) * LDY + 64, lane);
-                }
+                // The B-side fragments of k-step s + 1 are read while the
+                // products of k-step s issue; the A side and the centre
+                // operands are read in their own k-step (two waves per SIMD
+                // leave no registers for a second A set).
+                typename MW::afrag fa[2];
+                typename MW::bfrag fb[2][5];
+#pragma unroll
+                for (int j = 0; j < 5; ++j) fb[0][j] = MW::load_b(bq + kr0 * ldq + 16 * (q0 + j), lane);
 #pragma unroll
                 for (int s = 0; s < KT / 4; ++s) {
                     const int kr = 4 * s + kr0;
-                    rect_step<T, MW, 2, 5>(acc, bp + kr * ldp, bq + kr * ldq, p0, q0, lane);
+#pragma unroll
+                    for (int i = 0; i < 2; ++i) fa[i] = MW::load_a(bp + kr * ldp + 16 * (p0 + i), lane);
+                    if (s + 1 < KT / 4) {
+                        const int kn = kr + 4;
+#pragma unroll
+                        for (int j = 0; j < 5; ++j) fb[(s + 1) & 1][j] = MW::load_b(bq + kn * ldq + 16 * (q0 + j), lane);
+                    }
+                    rect_mma<T, MW, 2, 5>(acc, fa, fb[s & 1]);
+                    if (cs == s) {
+                        ca = M::load_a(bx + (4 * cs + kr0) * LDX + 64, lane);
+                        cb = M::load_b(by + (4 * cs + kr0) * LDY + 64, lane);
+                    }
                     if (cs == s) M::run(ca, cb, accc);
                 }
             }
