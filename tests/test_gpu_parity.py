@@ -235,3 +235,49 @@ def test_cfg2_full_size_sampled(oracle_mod):
     assert np.all(np.isfinite(got))
     assert np.max(np.abs(got - p.C)) <= K * np.max(np.abs(p.A)) * np.max(np.abs(p.B))
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_int64_offsets(oracle_mod, dtype):
+    """An operand whose span exceeds 2^31 bytes (one huge stride over a
+    length-2 dimension) takes the 64-bit offset kernels; checked under every
+    tile configuration."""
+    from paper_1607_00291_amd import tc
+    torch = require_gpu()
+    rng = np.random.default_rng(91)
+    e = {"a": 37, "e": 3, "b": 6, "f": 2, "d": 9, "c": 21}
+    A = inputs.colmajor_from_flat(rng.uniform(-1, 1, 37 * 3 * 6 * 2), (37, 3, 6, 2))
+    B = inputs.colmajor_from_flat(rng.uniform(-1, 1, 9 * 2 * 21 * 3), (9, 2, 21, 3))
+    C0 = inputs.colmajor_from_flat(rng.uniform(-1, 1, 37 * 6 * 21 * 9), (37, 6, 21, 9))
+    if dtype == np.float32:
+        A, B, C0 = (np.asfortranarray(x.astype(np.float32).astype(np.float64)) for x in (A, B, C0))
+    p = inputs.Problem("aebf", "dfce", "abcd", A, B, C0, 1.5, -0.5, "int64-offsets", e)
+    elt = np.dtype(dtype).itemsize
+    big = (1 << 31) // elt  # one step of this stride alone passes 2^31 bytes
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    storage = torch.zeros(big + 37 * 3 * 6, dtype=tdt, device="cuda")
+    Ad = torch.as_strided(storage, (37, 3, 6, 2), (1, 37, 111, big))
+    Ad.copy_(torch.from_numpy(A.astype(dtype)).to("cuda"))
+    Bd = to_dev(B, dtype)
+    ref = oracle_result(oracle_mod, p)
+    if dtype == np.float32:
+        absC = oracle_result(oracle_mod, inputs.Problem(p.idx_A, p.idx_B, p.idx_C, p.A, p.B,
+                                                        np.zeros_like(p.C, order="F"), 1.0, 0.0), absval=True)
+        bound = fp32_componentwise(p.mnk()[2], p.alpha, absC, p.beta, p.C)
+    code = tc.TC_F64 if dtype == np.float64 else tc.TC_F32
+    for t in range(tc.tile_count(code)):
+        Cd = to_dev(C0, dtype)
+        plan = tc.Plan.for_tensors(Ad, p.idx_A, Bd, p.idx_B, Cd, p.idx_C)
+        assert plan.describe()["off64"]
+        plan.tile = t
+        print(f"case int64 offsets dtype={np.dtype(dtype).name} tile={t}", flush=True)
+        plan.execute(Ad, Bd, Cd, p.alpha, p.beta)
+        plan.close()
+        torch.cuda.synchronize()
+        got = to_host(Cd).astype(np.float64)
+        if dtype == np.float64:
+            check_fp64(oracle_mod, p, got)
+        else:
+            assert np.all(np.abs(got - ref) <= bound + 1e-30), f"tile {t}"
+    del storage
+    torch.cuda.empty_cache()
