@@ -323,25 +323,65 @@ struct Pack {
     }
 };
 
-// alpha/beta update of one output element through rscat_C / cscat_C
-// (Sec. 6.1); C is read only when beta != 0.
-template <typename T, typename OffT>
-__device__ __forceinline__ void store_c(const KArgs<T, OffT>& a, OffT mm, OffT nn, T acc) {
-    if (mm < a.m && nn < a.n) {
-        const OffT o = a.rC[mm] + a.cC[nn];
-        T v = a.alpha * acc;
-        if (a.beta != T(0)) v += a.beta * a.C[o];
-        a.C[o] = v;
+// alpha/beta update of an R x C rectangle of accumulator fragments through
+// rscat_C / cscat_C (Sec. 6.1); C is read only when beta != 0.  Fragment
+// (i, j) covers fragment rows r0 + 16 i + M::row and columns c0 + 16 j +
+// M::col; they are C's m and n, or n and m when TR (a rectangle computed as
+// C^T).  The offset reads, the C reads of a fragment row and its stores are
+// each issued as one group, so a lane waits for two memory round trips per
+// fragment row rather than two per element.
+template <typename T, typename OffT, typename M, int R, int C, bool TR>
+__device__ __forceinline__ void store_rect(const KArgs<T, OffT>& a, const typename M::acc_t* acc, OffT r0, OffT c0,
+                                           int lane) {
+    const OffT rmax = TR ? a.n : a.m, cmax = TR ? a.m : a.n;
+    const OffT* rvec = TR ? a.cC : a.rC;
+    const OffT* cvec = TR ? a.rC : a.cC;
+    OffT co[C][4];
+    bool cok[C][4];
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const OffT c = (OffT)(c0 + 16 * j + M::col(lane, t));
+            cok[j][t] = c < cmax;
+            co[j][t] = cvec[cok[j][t] ? c : OffT(0)];
+        }
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        OffT ro[4];
+        bool rok[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const OffT r = (OffT)(r0 + 16 * i + M::row(lane, t));
+            rok[t] = r < rmax;
+            ro[t] = rvec[rok[t] ? r : OffT(0)];
+        }
+        T cv[C][4];
+        if (a.beta != T(0)) {
+#pragma unroll
+            for (int j = 0; j < C; ++j)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) cv[j][t] = a.C[rok[t] && cok[j][t] ? ro[t] + co[j][t] : OffT(0)];
+        }
+#pragma unroll
+        for (int j = 0; j < C; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (rok[t] && cok[j][t]) {
+                    T v = a.alpha * acc[i * C + j][t];
+                    if (a.beta != T(0)) v += a.beta * cv[j][t];
+                    a.C[ro[t] + co[j][t]] = v;
+                }
+            }
     }
 }
 
-// Store every element of one accumulator fragment whose origin in C's matrix
-// view is (fm0, fn0).
+// Store of one accumulator fragment whose origin in C's matrix view is
+// (fm0, fn0).
 template <typename T, typename OffT, typename M = Mfma<T>>
 __device__ __forceinline__ void store_frag(const KArgs<T, OffT>& a, OffT fm0, OffT fn0, const typename M::acc_t& acc,
                                            int lane) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) store_c(a, (OffT)(fm0 + M::row(lane, t)), (OffT)(fn0 + M::col(lane, t)), acc[t]);
+    store_rect<T, OffT, M, 1, 1, false>(a, &acc, fm0, fn0, lane);
 }
 
 // One k-step (depth 4) of an R x C rectangle of fragments whose origin is
@@ -381,11 +421,7 @@ __device__ __forceinline__ void rect_mma(typename M::acc_t* acc, const typename 
 template <typename T, typename OffT, typename M, int R, int C>
 __device__ __forceinline__ void rect_store(const KArgs<T, OffT>& a, const typename M::acc_t* acc, OffT m0, OffT n0,
                                            int fr0, int fc0, int lane) {
-#pragma unroll
-    for (int i = 0; i < R; ++i)
-#pragma unroll
-        for (int j = 0; j < C; ++j)
-            store_frag<T, OffT, M>(a, (OffT)(m0 + 16 * (fr0 + i)), (OffT)(n0 + 16 * (fc0 + j)), acc[i * C + j], lane);
+    store_rect<T, OffT, M, R, C, false>(a, acc, (OffT)(m0 + 16 * fr0), (OffT)(n0 + 16 * fc0), lane);
 }
 
 // Store of a rectangle computed as C^T: fragment (i, j) covers n-fragment
@@ -393,14 +429,7 @@ __device__ __forceinline__ void rect_store(const KArgs<T, OffT>& a, const typena
 template <typename T, typename OffT, typename M, int R, int C>
 __device__ __forceinline__ void rect_store_t(const KArgs<T, OffT>& a, const typename M::acc_t* acc, OffT m0, OffT n0,
                                              int fp0, int fq0, int lane) {
-#pragma unroll
-    for (int i = 0; i < R; ++i)
-#pragma unroll
-        for (int j = 0; j < C; ++j)
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                store_c(a, (OffT)(m0 + 16 * (fq0 + j) + M::col(lane, t)), (OffT)(n0 + 16 * (fp0 + i) + M::row(lane, t)),
-                        acc[i * C + j][t]);
+    store_rect<T, OffT, M, R, C, true>(a, acc, (OffT)(n0 + 16 * fp0), (OffT)(m0 + 16 * fq0), lane);
 }
 
 // Regular layout: a WM x WN grid of waves, each owning FM x FN fragments.
@@ -470,11 +499,7 @@ struct TileRegular {
             else pipeline(std::integral_constant<int, -1>());
         }
         // alpha/beta scatter-store through rscat_C / cscat_C (Sec. 6.1)
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-                store_frag(a, (OffT)(m0 + wm * WTM + 16 * i), (OffT)(n0 + wn * WTN + 16 * j), acc[i][j], lane);
+        store_rect<T, OffT, M, FM, FN, false>(a, &acc[0][0], (OffT)(m0 + wm * WTM), (OffT)(n0 + wn * WTN), lane);
     }
 };
 
@@ -921,12 +946,7 @@ struct TileSplit {
                 __syncthreads();
             }
         }
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-                store_frag<float, OffT, M>(a, (OffT)(m0 + wm * WTM + 16 * i), (OffT)(n0 + wn * WTN + 16 * j), acc[i][j],
-                                           lane);
+        store_rect<float, OffT, M, FM, FN, false>(a, &acc[0][0], (OffT)(m0 + wm * WTM), (OffT)(n0 + wn * WTN), lane);
     }
 };
 
