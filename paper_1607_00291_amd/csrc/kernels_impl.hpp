@@ -160,6 +160,7 @@ struct KArgs {
     int64_t spanX, spanY;  // element spans of X and Y (bounds of the buffer loads)
     T alpha, beta;
     int kregX, kregY;  // 1: every k block of X (Y) has a nonzero block stride
+    OffT ksX, ksY;     // the block stride shared by every k block of X (Y), else 0
 };
 
 // LDS row pitch (in elements) of a k-major stage: one element of padding when
@@ -531,6 +532,21 @@ struct PackRole {
                                          int t) {
         load_with<SL>(uniform(kbs[kb]), uniform(kvec[kb * KT]), base, span, kvec, kb, K, t);
     }
+    // Every k block shares the block stride s (REG = 2 below): the offset of
+    // element i relative to its block's first k offset is the same in every
+    // block, so it is formed once per tile, in bytes (out of range past the
+    // edge), and the k offsets of a block reach the loads as one scalar.
+    // tail: the elements that stay inside the last, partial block (bit i).
+    uint32_t tail = 0;
+    __device__ __forceinline__ void fix_offsets(OffT s, OffT K, int t) {
+        const OffT rem = K % KT;
+#pragma unroll
+        for (int i = 0; i < E; ++i) {
+            const OffT kk = (OffT)kidx(t + NTHR * i);
+            o[i] = o[i] >= 0 ? (OffT)((uint32_t)(o[i] + kk * s) * (uint32_t)sizeof(T)) : (OffT)kOutOfRange;
+            tail |= (uint32_t)(kk < rem) << i;
+        }
+    }
     // The same with the k block's stride and first k offset already in
     // scalar registers (fetched ahead by the caller).  REG = 1: the caller
     // knows every k block of this operand has a nonzero stride (no per-k
@@ -542,9 +558,20 @@ struct PackRole {
     __device__ __forceinline__ void load_with(OffT sk, OffT kfirst, const T* base, int64_t span, const OffT* kvec,
                                               OffT kb, OffT K, int t) {
         const OffT k0 = kb * KT;
+        if constexpr (REG == 2 && sizeof(OffT) == 4) {
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, span);
+            const uint32_t soff = (uint32_t)uniform((int32_t)((uint32_t)kfirst * (uint32_t)sizeof(T)));
+            const bool partial = k0 + KT > K;
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const uint32_t vo = partial && !((tail >> i) & 1u) ? kOutOfRange : (uint32_t)o[i];
+                r[SL][i] = buf_load<T>(rs, vo, soff);
+            }
+            return;
+        }
         OffT ko[E];
         OffT kbase = 0;
-        if (REG == 1 || (REG == -1 && sk)) {
+        if (REG >= 1 || (REG == -1 && sk)) {
             kbase = kfirst;
 #pragma unroll
             for (int i = 0; i < E; ++i) ko[i] = (OffT)kidx(t + NTHR * i) * sk;
@@ -731,8 +758,15 @@ struct TilePinwheel8 {
             }
         };
         if (nkb > 0) {
-            if (gx ? a.kregX : a.kregY) pipeline(std::integral_constant<int, 1>());
-            else pipeline(std::integral_constant<int, 0>());
+            const OffT ks = gx ? a.ksX : a.ksY;
+            if (sizeof(OffT) == 4 && ks != 0) {
+                pk.fix_offsets(ks, a.k, tt);
+                pipeline(std::integral_constant<int, 2>());
+            } else if (gx ? a.kregX : a.kregY) {
+                pipeline(std::integral_constant<int, 1>());
+            } else {
+                pipeline(std::integral_constant<int, 0>());
+            }
         }
         if (wide) rect_store<T, OffT, MW, 2, 5>(a, acc, m0, n0, fr0, fc0, lane);
         else rect_store_t<T, OffT, MW, 2, 5>(a, acc, m0, n0, fc0, fr0, lane);
@@ -1027,6 +1061,15 @@ static int launch_tile(const KArgs<T, OffT>& a, bool xm, bool yn, hipStream_t s)
     return e == hipSuccess ? TC_OK : hip_fail(e, "kernel launch");
 }
 
+// The block stride shared by every k block, or 0 when they differ or one
+// has none.
+static inline int64_t common_stride(const std::vector<int64_t>& kbs) {
+    if (kbs.empty() || kbs[0] == 0) return 0;
+    for (int64_t v : kbs)
+        if (v != kbs[0]) return 0;
+    return kbs[0];
+}
+
 template <typename T, typename OffT>
 static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B,
                         double beta, void* C, hipStream_t s) {
@@ -1054,6 +1097,8 @@ static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, co
     a.beta = (T)beta;
     a.kregX = p.k_blocks_regular_x == (int64_t)p.kbsX.size();
     a.kregY = p.k_blocks_regular_y == (int64_t)p.kbsY.size();
+    a.ksX = (OffT)common_stride(p.kbsX);
+    a.ksY = (OffT)common_stride(p.kbsY);
     if (p.m == 0 || p.n == 0) return TC_OK;
     if (p.k_empty || p.k == 0 || alpha == 0.0) {
         int64_t total = p.m * p.n;
@@ -1135,6 +1180,8 @@ __global__ __launch_bounds__(WM* WN * 64) void batch_kernel(const BatchItemDev* 
         a.beta = (T)it.beta;
         a.kregX = it.kregX;
         a.kregY = it.kregY;
+        a.ksX = 0;  // the batched (regular) tiles do not use it
+        a.ksY = 0;
         const int64_t tile = w - it.first_item;
         if (it.x_lanes_m) {
             if (it.y_lanes_n) TTT::run(a, tile, smem);
