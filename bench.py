@@ -1,6 +1,6 @@
 """Benchmark of the transpose-free contraction on one GPU.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick] [--tile T]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick] [--tile T] [--copy-calibration]
 
 Headline workload (value, roofline): the FP64 forward of the coupled-cluster
 shaped contraction Z[abij] = sum_{k,c} W[akic] T[cbkj] + Z with a,b,c = 96 and
@@ -10,8 +10,12 @@ contraction (one kernel launch); value = 2mnk / mean step time.
 The same line carries, under "secondary", the other workloads measured on the
 same GPU: FP32 and split-BF16 at the same shape, the FP32 forward + backward of
 C[ijab] = A[iklb] B[kjal] (i,j,k,l = 32, a,b = 64), the FP64 extent-16
-contraction C[abcd] = A[aebf] B[dfce], and 512 batched FP64 contractions in one
-persistent launch against 512 sequential launches (unless --quick).
+contraction C[abcd] = A[aebf] B[dfce], 512 batched FP64 contractions against
+512 sequential launches, and a sweep of random contractions (Sec. 9.2) against
+plain GEMMs of the same size (unless --quick).
+
+  --copy-calibration first runs a plain 1 GiB device copy three times in the
+  same process: the reference that scales rocprofv3's HBM byte counters.
 """
 import argparse
 import hashlib
@@ -237,8 +241,9 @@ def sweep(tc, inputs, steps, warmup, square=(512, 1024, 2048, 4096), rankk=(8, 3
 
 
 def batched(tc, inputs, steps, warmup):
-    """512 contractions (extents 4..64, random permutations) in one
-    persistent launch against 512 sequential plan launches."""
+    """512 contractions (extents 4..64, random permutations) as one batch
+    (persistent launches, one per tile class, or one class for all if the
+    autotuner finds that faster) against 512 sequential plan launches."""
     import torch
     probs, tensors, total = [], [], 0.0
     for i in range(512):

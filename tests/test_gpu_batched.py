@@ -1,5 +1,5 @@
-"""Batched contractions in one persistent launch: bitwise equality with
-sequential launches of the same tile configuration, parity with the oracle,
+"""Batched contractions in persistent launches (one per tile class): bitwise equality with
+sequential launches with a regular tile configuration, parity with the oracle,
 and graph capture with several replays."""
 import numpy as np
 import pytest
