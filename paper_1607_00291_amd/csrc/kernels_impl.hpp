@@ -1013,9 +1013,175 @@ struct TileOf {
     typedef TileRegular<T, OffT, MT, NT, KT, WM, WN, XM, YN> type;
     static constexpr int threads = WM * WN * 64;
 };
+// Pinwheel with specialised waves: waves 0-3 (one per SIMD) each own one
+// whole 4x5 / 5x4 rectangle of the pinwheel (a 5x4 one run as the 4x5
+// rectangle of C^T) plus one k-step of the centre fragment per stage, and only
+// read LDS and issue matrix instructions; waves 4-7 (one per SIMD) do every
+// gather (4 and 5 the X sliver, 6 and 7 the Y sliver) and the LDS stores, so
+// the compute waves never wait on vector-memory gathers.
+template <typename T, typename OffT, int KT, bool XM, bool YN>
+struct TilePinwheelWS {
+    static constexpr int MT = 144, NT = 144, NTHR = 512;
+    static_assert(KT % 4 == 0 && KT / 4 == 4, "one centre k-step per producer wave and stage");
+    static constexpr int SLOTS = 2;
+    typedef PackRole<T, OffT, 144, KT, 128, SLOTS> PR;
+    static constexpr int LDX = Pitch<MT, XM>::value, LDY = Pitch<NT, YN>::value;
+    static constexpr int XS = KT * LDX, YS = KT * LDY;
+    static constexpr int ELEMS = 2 * (XS + YS);
+    static constexpr int SMEM = ELEMS > 4 * 256 ? ELEMS : 4 * 256;
+    typedef typename MfmaFor<T, true>::type MW;
+
+    static __device__ __forceinline__ void run(const KArgs<T, OffT>& a, int64_t tile, T* smem) {
+        typedef Mfma<T> M;
+        typedef typename M::acc_t acc_t;
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int64_t tm = tile % a.tiles_m, tn = tile / a.tiles_m;
+        const OffT m0 = (OffT)(tm * MT), n0 = (OffT)(tn * NT);
+        const OffT nkb = (a.k + KT - 1) / KT;
+        if (wave >= 4) {
+            // ---- producer waves ----
+            const bool gx = wave < 6;
+            const int tt = tid & 127;
+            const T* gbase = gx ? a.X : a.Y;
+            const int64_t gspan = gx ? a.spanX : a.spanY;
+            const OffT* gk = gx ? a.cX : a.rY;
+            const OffT* gbs = gx ? a.kbsX : a.kbsY;
+            T* gstage = gx ? smem : smem + 2 * XS;
+            const int gsz = gx ? XS : YS;
+            PR pk;
+            if (gx) pk.init(a.rX, m0, a.m, tt, XM, LDX);
+            else pk.init(a.cY, n0, a.n, tt, YN, LDY);
+            // the centre fragment: producer wave w does k-step w - 4 of every
+            // stage
+            acc_t accc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) accc[r] = T(0);
+            const int kc = 4 * (wave - 4) + (lane >> 4);
+            OffT pre_sk = 0, pre_k = 0;
+            auto fetch = [&](OffT kb) {
+                pre_sk = uniform(gbs[kb]);
+                pre_k = uniform(gk[kb * KT]);
+            };
+            auto body = [&](OffT kb, auto slot, auto reg) {
+                constexpr int SL = decltype(slot)::value;
+                constexpr int RG = decltype(reg)::value;
+                const int buf = (int)(kb & 1);
+                const OffT lk = kb + 2 < nkb ? kb + 2 : nkb - 1;
+                pk.template load_with<SL, RG>(pre_sk, pre_k, gbase, gspan, gk, lk, a.k, tt);
+                fetch(kb + 3 < nkb ? kb + 3 : nkb - 1);
+                if (kb < nkb) {
+                    const typename M::afrag ca = M::load_a(smem + buf * XS + kc * LDX + 64, lane);
+                    const typename M::bfrag cb = M::load_b(smem + 2 * XS + buf * YS + kc * LDY + 64, lane);
+                    M::run(ca, cb, accc);
+                }
+                pk.template store<(SL + 1) % SLOTS>(gstage + (buf ^ 1) * gsz, tt);
+                __syncthreads();
+            };
+            auto pipeline = [&](auto reg) {
+                constexpr int RG = decltype(reg)::value;
+                fetch(0);
+                pk.template load_with<0, RG>(pre_sk, pre_k, gbase, gspan, gk, 0, a.k, tt);
+                pk.template store<0>(gstage, tt);
+                fetch(nkb > 1 ? 1 : 0);
+                pk.template load_with<1, RG>(pre_sk, pre_k, gbase, gspan, gk, nkb > 1 ? 1 : 0, a.k, tt);
+                fetch(nkb > 2 ? 2 : nkb - 1);
+                __syncthreads();
+                for (OffT kb = 0; kb < nkb; kb += 2) {
+                    body(kb, std::integral_constant<int, 0>(), reg);
+                    body(kb + 1, std::integral_constant<int, 1>(), reg);
+                }
+            };
+            if (nkb > 0) {
+                const OffT ks = gx ? a.ksX : a.ksY;
+                if (sizeof(OffT) == 4 && ks != 0) {
+                    pk.fix_offsets(ks, a.k, tt);
+                    pipeline(std::integral_constant<int, 2>());
+                } else if (gx ? a.kregX : a.kregY) {
+                    pipeline(std::integral_constant<int, 1>());
+                } else {
+                    pipeline(std::integral_constant<int, 0>());
+                }
+            }
+            // centre fragment: partial sums of the four producer waves added
+            // in wave order (the stage buffers are free after the last stage)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) smem[(wave - 4) * 256 + r * 64 + lane] = accc[r];
+            __syncthreads();
+            if (wave == 4) {
+                acc_t v;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    T x = smem[r * 64 + lane];
+#pragma unroll
+                    for (int w = 1; w < 4; ++w) x += smem[w * 256 + r * 64 + lane];
+                    v[r] = x;
+                }
+                store_frag(a, (OffT)(m0 + 64), (OffT)(n0 + 64), v, lane);
+            }
+            return;
+        }
+        // ---- compute waves ----
+        const int q = wave;
+        const bool wide = (q & 1) == 0;
+        const int fr0 = q == 0 ? 0 : q == 1 ? 0 : q == 2 ? 5 : 4;
+        const int fc0 = q == 0 ? 0 : q == 1 ? 5 : q == 2 ? 4 : 0;
+        const int p0 = wide ? fr0 : fc0, q0 = wide ? fc0 : fr0;
+        const int ldp = wide ? LDX : LDY, ldq = wide ? LDY : LDX;
+        acc_t acc[20];
+#pragma unroll
+        for (int f = 0; f < 20; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[f][r] = T(0);
+        const int kr0 = lane >> 4;
+        auto stage = [&](OffT kb) {
+            const int buf = (int)(kb & 1);
+            if (kb < nkb) {
+                const T* bx = smem + buf * XS;
+                const T* by = smem + 2 * XS + buf * YS;
+                const T* bp = wide ? bx : by;
+                const T* bq = wide ? by : bx;
+                typename MW::bfrag fb[5];
+#pragma unroll
+                for (int s = 0; s < KT / 4; ++s) {
+                    const int kr = 4 * s + kr0;
+#pragma unroll
+                    for (int j = 0; j < 5; ++j) fb[j] = MW::load_b(bq + kr * ldq + 16 * (q0 + j), lane);
+                    // one A fragment row at a time, the next one read over
+                    // the current row's products
+                    typename MW::afrag fa[2];
+                    fa[0] = MW::load_a(bp + kr * ldp + 16 * p0, lane);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (i + 1 < 4) fa[(i + 1) & 1] = MW::load_a(bp + kr * ldp + 16 * (p0 + i + 1), lane);
+#pragma unroll
+                        for (int j = 0; j < 5; ++j) MW::run(fa[i & 1], fb[j], acc[i * 5 + j]);
+                    }
+                }
+            }
+            __syncthreads();
+        };
+        if (nkb > 0) {
+            __syncthreads();  // the producers' first stage
+            for (OffT kb = 0; kb < nkb; kb += 2) {
+                stage(kb);
+                stage(kb + 1);
+            }
+        }
+        __syncthreads();  // the producers' centre reduction
+        if (wide) rect_store<T, OffT, MW, 4, 5>(a, acc, m0, n0, fr0, fc0, lane);
+        else rect_store_t<T, OffT, MW, 4, 5>(a, acc, m0, n0, fc0, fr0, lane);
+    }
+};
+
 template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
 struct TileOf<T, OffT, MT, NT, KT, WM, WN, 1, XM, YN> {
     typedef TilePinwheel8<T, OffT, KT, XM, YN> type;
+    static constexpr int threads = 512;
+};
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
+struct TileOf<T, OffT, MT, NT, KT, WM, WN, 2, XM, YN> {
+    typedef TilePinwheelWS<T, OffT, KT, XM, YN> type;
     static constexpr int threads = 512;
 };
 

@@ -17,7 +17,8 @@
     X(1, 64, 64, 16, 2, 2, 0)      \
     X(2, 128, 64, 16, 2, 2, 0)     \
     X(3, 128, 128, 16, 2, 2, 0)    \
-    X(4, 144, 144, 16, 1, 1, 1)
+    X(4, 144, 144, 16, 1, 1, 1)    \
+    X(5, 144, 144, 16, 1, 1, 2)
 
 #define TC_TILES_F32(X)            \
     X(0, 32, 32, 32, 1, 1, 0)      \
@@ -37,7 +38,7 @@ namespace tc {
 
 struct TileCfg {
     int MT, NT, KT, WM, WN, layout;
-    int waves() const { return layout == 1 ? 8 : WM * WN; }
+    int waves() const { return layout != 0 ? 8 : WM * WN; }
 };
 
 #define TC_TILE_ENTRY(id, MT, NT, KT, WM, WN, L) TileCfg{MT, NT, KT, WM, WN, L},
@@ -55,7 +56,7 @@ struct TileRate {
     double r1, r2;
     int occ;
 };
-static const TileRate kRatesF64[] = {{31, 31, 2}, {25, 46, 2}, {35, 52, 2}, {40.6, 40.6, 1}, {51.4, 51.4, 1}};
+static const TileRate kRatesF64[] = {{31, 31, 2}, {25, 46, 2}, {35, 52, 2}, {40.6, 40.6, 1}, {51.4, 51.4, 1}, {1, 1, 1}};
 static const TileRate kRatesF32[] = {{50, 54, 2}, {41, 86, 2}, {58, 94, 2}, {65, 96, 2}, {94, 94, 1}};
 static const TileRate kRatesBF16x3[] = {{45, 50, 2}, {38, 105, 2}, {59, 104, 2}, {76, 145, 2}};
 static_assert(sizeof(kRatesF64) / sizeof(TileRate) == sizeof(kTilesF64) / sizeof(TileCfg), "one rate per tile");
