@@ -25,6 +25,7 @@
 
 #include <cstdint>
 #include <type_traits>
+#include <utility>
 #include <cstdio>
 
 #include "launch.hpp"
@@ -507,6 +508,16 @@ struct TileRegular {
 // The pack stage of one operand, with the operand (and so the lane
 // direction and LDS pitch) chosen at run time: used where a wave gathers
 // either X or Y, so that only one set of gather registers is live.
+// Calls f(std::integral_constant<int, I>()) for I = 0 .. N-1 in order.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>()), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>());
+}
+
 template <typename T, typename OffT, int R, int KT, int NTHR, int SLOTS = 1>
 struct PackRole {
     static constexpr int E = R * KT / NTHR;
@@ -1022,8 +1033,10 @@ struct TileOf {
 template <typename T, typename OffT, int KT, bool XM, bool YN>
 struct TilePinwheelWS {
     static constexpr int MT = 144, NT = 144, NTHR = 512;
-    static_assert(KT % 4 == 0 && KT / 4 == 4, "one centre k-step per producer wave and stage");
-    static constexpr int SLOTS = 2;
+    static_assert(KT % 16 == 0, "the centre's k-steps split evenly over the four producer waves");
+    // gathered stages in flight per producer thread (three measured best for
+    // FP64; FP32's larger stages leave registers for one)
+    static constexpr int SLOTS = sizeof(T) == 8 ? 3 : 1;
     typedef PackRole<T, OffT, 144, KT, 128, SLOTS> PR;
     static constexpr int LDX = Pitch<MT, XM>::value, LDY = Pitch<NT, YN>::value;
     static constexpr int XS = KT * LDX, YS = KT * LDY;
@@ -1052,8 +1065,8 @@ struct TilePinwheelWS {
             PR pk;
             if (gx) pk.init(a.rX, m0, a.m, tt, XM, LDX);
             else pk.init(a.cY, n0, a.n, tt, YN, LDY);
-            // the centre fragment: producer wave w does k-step w - 4 of every
-            // stage
+            // the centre fragment: producer wave w does k-steps w - 4, w, ...
+            // of every stage
             acc_t accc;
 #pragma unroll
             for (int r = 0; r < 4; ++r) accc[r] = T(0);
@@ -1067,13 +1080,17 @@ struct TilePinwheelWS {
                 constexpr int SL = decltype(slot)::value;
                 constexpr int RG = decltype(reg)::value;
                 const int buf = (int)(kb & 1);
-                const OffT lk = kb + 2 < nkb ? kb + 2 : nkb - 1;
+                const OffT lk = kb + SLOTS < nkb ? kb + SLOTS : nkb - 1;
                 pk.template load_with<SL, RG>(pre_sk, pre_k, gbase, gspan, gk, lk, a.k, tt);
-                fetch(kb + 3 < nkb ? kb + 3 : nkb - 1);
+                fetch(kb + SLOTS + 1 < nkb ? kb + SLOTS + 1 : nkb - 1);
                 if (kb < nkb) {
-                    const typename M::afrag ca = M::load_a(smem + buf * XS + kc * LDX + 64, lane);
-                    const typename M::bfrag cb = M::load_b(smem + 2 * XS + buf * YS + kc * LDY + 64, lane);
-                    M::run(ca, cb, accc);
+#pragma unroll
+                    for (int c = 0; c < KT / 16; ++c) {
+                        const int kk = kc + 16 * c;
+                        const typename M::afrag ca = M::load_a(smem + buf * XS + kk * LDX + 64, lane);
+                        const typename M::bfrag cb = M::load_b(smem + 2 * XS + buf * YS + kk * LDY + 64, lane);
+                        M::run(ca, cb, accc);
+                    }
                 }
                 pk.template store<(SL + 1) % SLOTS>(gstage + (buf ^ 1) * gsz, tt);
                 __syncthreads();
@@ -1083,14 +1100,15 @@ struct TilePinwheelWS {
                 fetch(0);
                 pk.template load_with<0, RG>(pre_sk, pre_k, gbase, gspan, gk, 0, a.k, tt);
                 pk.template store<0>(gstage, tt);
-                fetch(nkb > 1 ? 1 : 0);
-                pk.template load_with<1, RG>(pre_sk, pre_k, gbase, gspan, gk, nkb > 1 ? 1 : 0, a.k, tt);
-                fetch(nkb > 2 ? 2 : nkb - 1);
+                static_for<SLOTS - 1>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value + 1;
+                    fetch(nkb > i ? i : nkb - 1);
+                    pk.template load_with<i, RG>(pre_sk, pre_k, gbase, gspan, gk, nkb > i ? i : nkb - 1, a.k, tt);
+                });
+                fetch(nkb > SLOTS ? SLOTS : nkb - 1);
                 __syncthreads();
-                for (OffT kb = 0; kb < nkb; kb += 2) {
-                    body(kb, std::integral_constant<int, 0>(), reg);
-                    body(kb + 1, std::integral_constant<int, 1>(), reg);
-                }
+                for (OffT kb = 0; kb < nkb; kb += SLOTS)
+                    static_for<SLOTS>([&](auto ic) { body(kb + decltype(ic)::value, ic, reg); });
             };
             if (nkb > 0) {
                 const OffT ks = gx ? a.ksX : a.ksY;
@@ -1163,10 +1181,9 @@ struct TilePinwheelWS {
         };
         if (nkb > 0) {
             __syncthreads();  // the producers' first stage
-            for (OffT kb = 0; kb < nkb; kb += 2) {
-                stage(kb);
-                stage(kb + 1);
-            }
+            for (OffT kb = 0; kb < nkb; kb += SLOTS)
+#pragma unroll
+                for (int i = 0; i < SLOTS; ++i) stage(kb + i);
         }
         __syncthreads();  // the producers' centre reduction
         if (wide) rect_store<T, OffT, MW, 4, 5>(a, acc, m0, n0, fr0, fc0, lane);

@@ -9,7 +9,9 @@
 //            centre fragment of the 9x9 grid, each halved between two waves,
 //            the centre's k-range split over the eight waves, so that every
 //            SIMD does exactly 20.25 fragments of work and 2304^2 outputs
-//            make exactly 256 tiles
+//            make exactly 256 tiles; 2 = the same pinwheel with specialised
+//            waves: four compute waves own one whole rectangle each, four
+//            producer waves gather both operands and do the centre
 #pragma once
 
 #define TC_TILES_F64(X)            \
@@ -25,7 +27,8 @@
     X(1, 64, 64, 32, 2, 2, 0)      \
     X(2, 128, 64, 32, 2, 2, 0)     \
     X(3, 128, 128, 32, 2, 2, 0)    \
-    X(4, 144, 144, 32, 1, 1, 1)
+    X(4, 144, 144, 32, 1, 1, 1)    \
+    X(5, 144, 144, 32, 1, 1, 2)
 
 // split-bf16: KT is a multiple of the bf16 MFMA depth (32)
 #define TC_TILES_BF16X3(X)         \
@@ -56,8 +59,8 @@ struct TileRate {
     double r1, r2;
     int occ;
 };
-static const TileRate kRatesF64[] = {{31, 31, 2}, {25, 46, 2}, {35, 52, 2}, {40.6, 40.6, 1}, {51.4, 51.4, 1}, {1, 1, 1}};
-static const TileRate kRatesF32[] = {{50, 54, 2}, {41, 86, 2}, {58, 94, 2}, {65, 96, 2}, {94, 94, 1}};
+static const TileRate kRatesF64[] = {{31, 31, 2}, {25, 46, 2}, {35, 52, 2}, {40.6, 40.6, 1}, {51.4, 51.4, 1}, {54.5, 54.5, 1}};
+static const TileRate kRatesF32[] = {{50, 54, 2}, {41, 86, 2}, {58, 94, 2}, {65, 96, 2}, {94, 94, 1}, {110, 110, 1}};
 static const TileRate kRatesBF16x3[] = {{45, 50, 2}, {38, 105, 2}, {59, 104, 2}, {76, 145, 2}};
 static_assert(sizeof(kRatesF64) / sizeof(TileRate) == sizeof(kTilesF64) / sizeof(TileCfg), "one rate per tile");
 static_assert(sizeof(kRatesF32) / sizeof(TileRate) == sizeof(kTilesF32) / sizeof(TileCfg), "one rate per tile");
