@@ -319,13 +319,14 @@ void set_plan_tile(Plan* p, int tile) {
 // rounds (wave quantisation over the chip's 256 CUs, with up to `occ`
 // workgroups resident per CU and the measured rate for that residency),
 // bounded below by the time to stream every tile's A and B slivers from the
-// caches (small tiles re-read the operands many times).  Earlier tiles win
-// ties.
+// caches (small tiles re-read the operands many times), plus the C update of
+// each round at the tile's relative store speed (what decides short-k,
+// output-bound shapes).  Earlier tiles win ties.
 int choose_tile(const Plan& p, bool regular_only) {
     const TileCfg* tab = tile_table(p.dtype, p.mode);
     const TileRate* rate = rate_table(p.dtype, p.mode);
     const int nt = tile_count(p.dtype, p.mode);
-    const double cus = 256.0, cache_bw = 4e12;
+    const double cus = 256.0, cache_bw = 4e12, hbm_bw = 5e12;
     const double esize = p.dtype == TC_F64 ? 8.0 : 4.0;
     const double k = (double)std::max<int64_t>(p.k, 1);
     int best = 0;
@@ -339,7 +340,8 @@ int choose_tile(const Plan& p, bool regular_only) {
         const double r = (w >= 2.0 ? rate[i].r2 : rate[i].r1) * 1e12 / cus;  // flop/s of one CU
         const double compute = rounds * w * 2.0 * t.MT * t.NT * k / r;
         const double stream = tiles * (double)(t.MT + t.NT) * k * esize / cache_bw;
-        const double time = std::max(compute, stream);
+        const double store = rounds * w * cus * (double)t.MT * t.NT * esize / (hbm_bw * rate[i].store);
+        const double time = std::max(compute, stream) + store;
         if (time < best_t * 0.999) {
             best_t = time;
             best = i;

@@ -53,15 +53,20 @@ static const TileCfg kTilesBF16x3[] = {TC_TILES_BF16X3(TC_TILE_ENTRY)};
 // Measured throughput of each tile configuration on MI355X (TFLOP/s, dense
 // column-major contractions of shapes 4096^2 x 1024, 2304^3, 2048^2 x 1024
 // and 1024^2 x 4096): r1 with one workgroup per compute unit, r2 with two or
-// more resident, occ the workgroups that fit on one compute unit at once.
-// The planner's cost model (choose_tile) is built on these figures.
+// more resident, occ the workgroups that fit on one compute unit at once, and
+// store the relative speed of the tile's C update (0.7 where only four of the
+// eight waves store: the output-store-bound rank-k shapes run about that much
+// slower on it).  The planner's cost model (choose_tile) is built on these.
 struct TileRate {
     double r1, r2;
     int occ;
+    double store;
 };
-static const TileRate kRatesF64[] = {{31, 31, 2}, {25, 46, 2}, {35, 52, 2}, {40.6, 40.6, 1}, {51.4, 51.4, 1}, {54.5, 54.5, 1}};
-static const TileRate kRatesF32[] = {{50, 54, 2}, {41, 86, 2}, {58, 94, 2}, {65, 96, 2}, {94, 94, 1}, {110, 110, 1}};
-static const TileRate kRatesBF16x3[] = {{45, 50, 2}, {38, 105, 2}, {59, 104, 2}, {76, 145, 2}};
+static const TileRate kRatesF64[] = {{31, 31, 2, 1},     {25, 46, 2, 1},     {35, 52, 2, 1},
+                                     {40.6, 40.6, 1, 1}, {51.4, 51.4, 1, 1}, {54.5, 54.5, 1, 0.7}};
+static const TileRate kRatesF32[] = {{50, 54, 2, 1}, {41, 86, 2, 1}, {58, 94, 2, 1},
+                                     {65, 96, 2, 1}, {94, 94, 1, 1}, {110, 110, 1, 0.7}};
+static const TileRate kRatesBF16x3[] = {{45, 50, 2, 1}, {38, 105, 2, 1}, {59, 104, 2, 1}, {76, 145, 2, 1}};
 static_assert(sizeof(kRatesF64) / sizeof(TileRate) == sizeof(kTilesF64) / sizeof(TileCfg), "one rate per tile");
 static_assert(sizeof(kRatesF32) / sizeof(TileRate) == sizeof(kTilesF32) / sizeof(TileCfg), "one rate per tile");
 static_assert(sizeof(kRatesBF16x3) / sizeof(TileRate) == sizeof(kTilesBF16x3) / sizeof(TileCfg), "one rate per tile");
