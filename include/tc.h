@@ -176,22 +176,23 @@ int tc_batch_execute(const tc_batch* batch, void* stream);
 int tc_batch_destroy(tc_batch* batch);
 /* Work-item count, the tile configuration (-1: per-problem classes) and the
  * largest persistent grid of the batch.  By default every problem runs with
- * the regular tile configuration the planner's cost model picks for it alone;
+ * the tile configuration the planner's cost model picks for it alone;
  * problems of one class share one persistent launch (so a batch issues at
- * most one launch per regular configuration, the class with the most work
+ * most one launch per configuration, the class with the most work
  * first), laid out in decreasing order of k (the cost of one tile) so that
  * the workgroups' static stride over the work list is balanced.  All regular
  * configurations of a dtype share KT, so each output element is summed in
  * the same order as by tc_plan_execute with any regular tile (bitwise
- * equal). */
+ * equal); the specialised-wave pinwheel (layout 2) sums its centre fragment
+ * in another order. */
 int tc_batch_info(const tc_batch* batch, int64_t* work_items, int* tile, int* grid);
-/* Set one tile configuration for the whole batch (regular layouts only), or
- * -1 for per-problem classes; re-uploads the work table (synchronous, not
- * during capture). */
+/* Set one tile configuration for the whole batch (any layout but the
+ * all-compute pinwheel, layout 1), or -1 for per-problem classes; re-uploads
+ * the work table (synchronous, not during capture). */
 int tc_batch_set_tile(tc_batch* batch, int tile);
 /* Autotuner for batches: times the whole batch (reps runs after one warm-up,
  * hipEvent timing on `stream`) with per-problem classes and under every
- * single regular tile configuration, and keeps the fastest.  Runs the batch
+ * single tile configuration a batch runs, and keeps the fastest.  Runs the batch
  * (1 + reps) times per candidate, so outputs with beta != 0 are updated
  * repeatedly: tune on scratch outputs.  Synchronises `stream`.  *best_ms may
  * be NULL. */

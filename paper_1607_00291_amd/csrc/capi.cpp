@@ -620,7 +620,7 @@ static int batch_create(tc_batch** out, int count, const tc_plan* const* plans, 
         it.kregX = p.k_blocks_regular_x == (int64_t)p.kbsX.size();
         it.kregY = p.k_blocks_regular_y == (int64_t)p.kbsY.size();
         b->host.push_back(it);
-        b->best.push_back(choose_tile(p, true));
+        b->best.push_back(choose_tile(p, true));  // layouts a batch runs
     }
     if (total) {
         hipError_t e = hipMemcpy(b->vectors, host.data(), total * w, hipMemcpyHostToDevice);
@@ -684,8 +684,8 @@ int tc_batch_set_tile(tc_batch* batch, int tile) {
         return TC_ERR_NULL;
     }
     if (tile < -1 || tile >= tile_count(batch->dtype, batch->mode) ||
-        (tile >= 0 && tile_table(batch->dtype, batch->mode)[tile].layout != 0)) {
-        set_error("not a regular tile configuration of this dtype/mode");
+        (tile >= 0 && tile_table(batch->dtype, batch->mode)[tile].layout == 1)) {
+        set_error("not a tile configuration batches run (regular or specialised-wave) of this dtype/mode");
         return TC_ERR_ARG;
     }
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -716,7 +716,7 @@ int tc_batch_autotune(tc_batch* batch, int reps, void* stream, double* best_ms) 
     float best_t = 1e30f;
     const int nt = tile_count(batch->dtype, batch->mode);
     for (int t = -1; t < nt && st == TC_OK; ++t) {  // -1: every problem with its own class
-        if (t >= 0 && tile_table(batch->dtype, batch->mode)[t].layout != 0) continue;
+        if (t >= 0 && tile_table(batch->dtype, batch->mode)[t].layout == 1) continue;
         if ((st = tc_batch_set_tile(batch, t))) break;
         if ((st = tc_batch_execute(batch, s))) break;  // warm-up
         hipEventRecord(e0, s);

@@ -1322,13 +1322,13 @@ static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, co
 // cost per tile, so the static stride assignment stays balanced.  Every
 // problem may have its own lane directions, so the four pack variants are
 // dispatched per item.
-template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN>
-__global__ __launch_bounds__(WM* WN * 64) void batch_kernel(const BatchItemDev* __restrict__ items, int count,
-                                                           int64_t total) {
-    typedef TileRegular<T, OffT, MT, NT, KT, WM, WN, true, true> TTT;
-    typedef TileRegular<T, OffT, MT, NT, KT, WM, WN, true, false> TTF;
-    typedef TileRegular<T, OffT, MT, NT, KT, WM, WN, false, true> TFT;
-    typedef TileRegular<T, OffT, MT, NT, KT, WM, WN, false, false> TFF;
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int L>
+__global__ __launch_bounds__((TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, true>::threads)) void batch_kernel(
+    const BatchItemDev* __restrict__ items, int count, int64_t total) {
+    typedef typename TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, true>::type TTT;
+    typedef typename TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, false>::type TTF;
+    typedef typename TileOf<T, OffT, MT, NT, KT, WM, WN, L, false, true>::type TFT;
+    typedef typename TileOf<T, OffT, MT, NT, KT, WM, WN, L, false, false>::type TFF;
     constexpr int S1 = TTT::SMEM > TTF::SMEM ? TTT::SMEM : TTF::SMEM;
     constexpr int S2 = TFT::SMEM > TFF::SMEM ? TFT::SMEM : TFF::SMEM;
     __shared__ T smem[S1 > S2 ? S1 : S2];
@@ -1363,7 +1363,7 @@ __global__ __launch_bounds__(WM* WN * 64) void batch_kernel(const BatchItemDev* 
         a.beta = (T)it.beta;
         a.kregX = it.kregX;
         a.kregY = it.kregY;
-        a.ksX = 0;  // the batched (regular) tiles do not use it
+        a.ksX = 0;  // per-tile byte offsets are not formed in batched launches
         a.ksY = 0;
         const int64_t tile = w - it.first_item;
         if (it.x_lanes_m) {
@@ -1379,26 +1379,27 @@ __global__ __launch_bounds__(WM* WN * 64) void batch_kernel(const BatchItemDev* 
 
 template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int L>
 struct BatchLaunch {
+    static constexpr int threads = TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, true>::threads;
     static int launch(const BatchItemDev* items, int count, int64_t total, int grid, hipStream_t s) {
-        if constexpr (L != 0) {
-            set_error("batched launches use the regular tile layouts");
+        if constexpr (L == 1) {
+            set_error("batched launches use the regular and specialised-wave layouts");
             return TC_ERR_ARG;
         } else {
-            hipLaunchKernelGGL((batch_kernel<T, OffT, MT, NT, KT, WM, WN>), dim3(grid), dim3(WM * WN * 64), 0, s,
+            hipLaunchKernelGGL((batch_kernel<T, OffT, MT, NT, KT, WM, WN, L>), dim3(grid), dim3(threads), 0, s,
                                items, count, total);
             hipError_t e = hipGetLastError();
             return e == hipSuccess ? TC_OK : hip_fail(e, "batched kernel launch");
         }
     }
     static int grid(int64_t total) {
-        if constexpr (L != 0) {
+        if constexpr (L == 1) {
             return 0;
         } else {
             int dev = 0, cus = 0, per_cu = 0;
             if (hipGetDevice(&dev) != hipSuccess) return 0;
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, (const void*)batch_kernel<T, OffT, MT, NT, KT, WM, WN>, WM * WN * 64, 0) != hipSuccess)
+                    &per_cu, (const void*)batch_kernel<T, OffT, MT, NT, KT, WM, WN, L>, threads, 0) != hipSuccess)
                 return 0;
             int64_t g = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
             return (int)(total < g ? total : g);

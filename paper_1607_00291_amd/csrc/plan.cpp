@@ -322,7 +322,7 @@ void set_plan_tile(Plan* p, int tile) {
 // caches (small tiles re-read the operands many times), plus the C update of
 // each round at the tile's relative store speed (what decides short-k,
 // output-bound shapes).  Earlier tiles win ties.
-int choose_tile(const Plan& p, bool regular_only) {
+int choose_tile(const Plan& p, bool batched) {
     const TileCfg* tab = tile_table(p.dtype, p.mode);
     const TileRate* rate = rate_table(p.dtype, p.mode);
     const int nt = tile_count(p.dtype, p.mode);
@@ -333,7 +333,7 @@ int choose_tile(const Plan& p, bool regular_only) {
     double best_t = 1e300;
     for (int i = 0; i < nt; ++i) {
         const TileCfg& t = tab[i];
-        if (regular_only && t.layout != 0) continue;
+        if (batched && t.layout == 1) continue;
         const double tiles = (double)((p.m + t.MT - 1) / t.MT) * (double)((p.n + t.NT - 1) / t.NT);
         const double w = std::min((double)rate[i].occ, std::ceil(tiles / cus));
         const double rounds = std::ceil(tiles / (cus * w));
