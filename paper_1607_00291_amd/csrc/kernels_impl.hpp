@@ -386,31 +386,8 @@ __device__ __forceinline__ void store_frag(const KArgs<T, OffT>& a, OffT fm0, Of
     store_rect<T, OffT, M, 1, 1, false>(a, &acc, fm0, fn0, lane);
 }
 
-// One k-step (depth 4) of an R x C rectangle of fragments whose origin is
-// fragment (fr0, fc0); bx / by point at LDS row kr of the X / Y stage.
-template <typename T, typename M, int R, int C>
-__device__ __forceinline__ void rect_step(typename M::acc_t* acc, const T* bx, const T* by, int fr0, int fc0, int lane) {
-    typename M::afrag fa[R];
-    typename M::bfrag fb[C];
-#pragma unroll
-    for (int i = 0; i < R; ++i) fa[i] = M::load_a(bx + 16 * (fr0 + i), lane);
-#pragma unroll
-    for (int j = 0; j < C; ++j) fb[j] = M::load_b(by + 16 * (fc0 + j), lane);
-#pragma unroll
-    for (int i = 0; i < R; ++i)
-#pragma unroll
-        for (int j = 0; j < C; ++j) M::run(fa[i], fb[j], acc[i * C + j]);
-}
-
-template <typename T, typename M, int R, int C>
-__device__ __forceinline__ void rect_load(typename M::afrag* fa, typename M::bfrag* fb, const T* bx, const T* by,
-                                          int fr0, int fc0, int lane) {
-#pragma unroll
-    for (int i = 0; i < R; ++i) fa[i] = M::load_a(bx + 16 * (fr0 + i), lane);
-#pragma unroll
-    for (int j = 0; j < C; ++j) fb[j] = M::load_b(by + 16 * (fc0 + j), lane);
-}
-
+// One k-step (depth 4) of an R x C rectangle of fragments: the products of
+// A fragment rows fa[0..R) with B fragment columns fb[0..C).
 template <typename T, typename M, int R, int C>
 __device__ __forceinline__ void rect_mma(typename M::acc_t* acc, const typename M::afrag* fa,
                                          const typename M::bfrag* fb) {
