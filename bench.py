@@ -346,7 +346,7 @@ def main():
         "wall_s_timed_region": round(wall, 3),
     }
     if not args.quick:
-        line["secondary"] = secondary(tc, inputs, max(args.steps // 5, 5), 2, False)
+        line["secondary"] = secondary(tc, inputs, max(args.steps // 2, 10), max(args.warmup, 5), False)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)
