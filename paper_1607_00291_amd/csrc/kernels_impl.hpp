@@ -827,13 +827,16 @@ struct PackPair {
             o[i] = rr < rmax ? x : OffT(-1);
         }
     }
+    // REG = 1: every k block of this operand has a block stride (no per-k
+    // offset reads compiled in); REG = -1: decided per block.
+    template <int REG = -1>
     __device__ __forceinline__ void load(const float* base, int64_t span, const OffT* kvec, const OffT* kbs, OffT kb,
                                          OffT K, int t) {
         const OffT k0 = kb * KT;
         const OffT sk = uniform(kbs[kb]);
         OffT kbase = 0;
         OffT ko0[EP], ko1[EP];
-        if (sk) {
+        if (REG == 1 || sk) {
             kbase = uniform(kvec[k0]);
 #pragma unroll
             for (int i = 0; i < EP; ++i) {
@@ -924,18 +927,25 @@ struct TileSplit {
         auto xs = [&](int buf) { return smem + buf * STAGE; };
         auto ys = [&](int buf) { return smem + buf * STAGE + 2 * PX::PLANE; };
         const OffT nkb = (a.k + KT - 1) / KT;
-        if (nkb > 0) {
-            px.load(a.X, a.spanX, a.cX, a.kbsX, 0, a.k, tid);
-            py.load(a.Y, a.spanY, a.rY, a.kbsY, 0, a.k, tid);
+        // the gathers of stage kb + 1 and their LDS store run with no branch
+        // around them (past the last stage they re-read the last block and
+        // fill the LDS buffer no stage reads any more), and a regular-k
+        // operand pair gets its own compiled path; the 128 x 128 tile keeps
+        // the guarded form, which measured faster for it
+        constexpr bool BF = !(MT == 128 && NT == 128);
+        auto pipeline = [&](auto reg) {
+            constexpr int RG = decltype(reg)::value;
+            px.template load<RG>(a.X, a.spanX, a.cX, a.kbsX, 0, a.k, tid);
+            py.template load<RG>(a.Y, a.spanY, a.rY, a.kbsY, 0, a.k, tid);
             px.store((uint32_t*)xs(0), tid);
             py.store((uint32_t*)ys(0), tid);
             __syncthreads();
             for (OffT kb = 0; kb < nkb; ++kb) {
                 const int buf = (int)(kb & 1);
-                const bool more = kb + 1 < nkb;
-                if (more) {
-                    px.load(a.X, a.spanX, a.cX, a.kbsX, kb + 1, a.k, tid);
-                    py.load(a.Y, a.spanY, a.rY, a.kbsY, kb + 1, a.k, tid);
+                const OffT kn = kb + 1 < nkb ? kb + 1 : kb;
+                if (BF || kb + 1 < nkb) {
+                    px.template load<RG>(a.X, a.spanX, a.cX, a.kbsX, kn, a.k, tid);
+                    py.template load<RG>(a.Y, a.spanY, a.rY, a.kbsY, kn, a.k, tid);
                 }
                 const __bf16* xh = xs(buf) + (wm * WTM + (lane & 15)) * PX::KTP + 8 * (lane >> 4);
                 const __bf16* yh = ys(buf) + (wn * WTN + (lane & 15)) * PY::KTP + 8 * (lane >> 4);
@@ -961,12 +971,16 @@ struct TileSplit {
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
                         }
                 }
-                if (more) {
+                if (BF || kb + 1 < nkb) {
                     px.store((uint32_t*)xs(buf ^ 1), tid);
                     py.store((uint32_t*)ys(buf ^ 1), tid);
                 }
                 __syncthreads();
             }
+        };
+        if (nkb > 0) {
+            if (BF && a.kregX && a.kregY) pipeline(std::integral_constant<int, 1>());
+            else pipeline(std::integral_constant<int, -1>());
         }
         store_rect<float, OffT, M, FM, FN, false>(a, &acc[0][0], (OffT)(m0 + wm * WTM), (OffT)(n0 + wn * WTN), lane);
     }
