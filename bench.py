@@ -11,8 +11,10 @@ The same line carries, under "secondary", the other workloads measured on the
 same GPU: FP32 and split-BF16 at the same shape, the FP32 forward + backward of
 C[ijab] = A[iklb] B[kjal] (i,j,k,l = 32, a,b = 64), the FP64 extent-16
 contraction C[abcd] = A[aebf] B[dfce], 512 batched FP64 contractions against
-512 sequential launches, and a sweep of random contractions (Sec. 9.2) against
-plain GEMMs of the same size (unless --quick).
+512 sequential launches, the transpose-transpose-GEMM-transpose method
+(Sec. 3.2) on the same GPU at the v=96/o=24 and the FP32 forward shapes, and a
+sweep of random contractions (Sec. 9.2) against plain GEMMs of the same size
+(unless --quick).
 
   --copy-calibration first runs a plain 1 GiB device copy three times in the
   same process: the reference that scales rocprofv3's HBM byte counters.
@@ -189,10 +191,49 @@ def secondary(tc, inputs, steps, warmup, quick):
     plan.close()
     del A, B, C
     if not quick:
+        out["ttgt_baseline"] = ttgt_baseline(tc, inputs, steps, warmup)
         out["batched_512_fp64"] = batched(tc, inputs, steps, warmup)
         out["random_sweep_fp64"] = sweep(tc, inputs, max(steps // 2, 5), 2)
     torch.cuda.empty_cache()
     return out
+
+
+def ttgt_baseline(tc, inputs, steps, warmup):
+    """The transpose-transpose-GEMM-transpose method (Sec. 3.2) on the same
+    GPU: permute-copies into matrix layout, one matrix product of the same
+    kernels, permute-copy back; against the transpose-free contraction."""
+    import torch
+    res = {}
+    cases = (("fp64_v96_o24", inputs.cfg2(), None, 1.0),
+             ("fp32_ijab_iklb_kjal_fwd", inputs.cfg4(), np.float32, 0.0))
+    for key, p, dt, beta in cases:
+        A, B, C = dev(p.A, dt), dev(p.B, dt), dev(p.C, dt)
+        plan, run = plan_runner(tc, A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, beta)
+        ms_free = time_calls(run, steps, warmup)
+        plan.close()
+        t = tc.TTGT(A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, beta)
+        ms_in = time_calls(t.transpose_in, steps, warmup)
+        ms_gemm = time_calls(t.gemm, steps, warmup)
+        ms_out = time_calls(t.transpose_out, steps, warmup)
+        ms_all = time_calls(t.run, steps, warmup)
+        elt = A.element_size()
+        moved = A.numel() + B.numel() + C.numel() * (2 if beta != 0.0 else 1)  # elements permuted per run
+        fl = 2.0 * t.m * t.n * t.k
+        res[key] = {
+            "transpose_free_ms": round(ms_free, 4),
+            "ttgt_ms": round(ms_all, 4),
+            "ttgt_over_transpose_free": round(ms_all / ms_free, 3),
+            "transpose_ms": round(ms_in + ms_out, 4),
+            "gemm_ms": round(ms_gemm, 4),
+            "transpose_fraction": round((ms_in + ms_out) / (ms_in + ms_gemm + ms_out), 4),
+            "permute_gbps": round(2.0 * elt * moved / ((ms_in + ms_out) * 1e6), 1),
+            "gemm_gflops": round(fl / ms_gemm / 1e6, 1),
+            "extra_workspace_bytes": t.workspace_bytes(),
+        }
+        t.close()
+        del A, B, C, t
+        torch.cuda.empty_cache()
+    return res
 
 
 def sweep(tc, inputs, steps, warmup, square=(512, 1024, 2048, 4096), rankk=(8, 32, 128, 512), big=4096, seeds=3):

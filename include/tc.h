@@ -211,6 +211,23 @@ int tc_batch_autotune(tc_batch* batch, int reps, void* stream, double* best_ms);
 int tc_scatter_vector(int ndim, const int64_t* lens, const int64_t* strides, int64_t* out);
 int tc_block_strides(const int64_t* scat, int64_t len, int64_t b, int64_t* out);
 
+/*
+ * Strided permute-copy, the explicit transposition of the
+ * transpose-transpose-GEMM-transpose method (Sec. 3.2) that the contraction
+ * above avoids; it lets that method be timed on the same device.
+ * dst[x . dst_strides] = src[x . src_strides] for every multi-index x over
+ * lens (ndim dimensions, ndim in [0, TC_MAX_NDIM]; strides in elements, > 0 on
+ * dimensions of length > 1).  src and dst are device pointers owned by the
+ * caller, of the storage type `dtype` (TC_F64 or TC_F32); element bits are
+ * copied unchanged.  dst must not overlap src, and distinct x must reach
+ * distinct dst elements; neither is checked (as with memcpy).  Asynchronous on
+ * `stream`; an empty index space is a no-op.  Errors: TC_ERR_NDIM,
+ * TC_ERR_NULL, TC_ERR_DTYPE, TC_ERR_EXTENT (negative length), TC_ERR_STRIDE,
+ * TC_ERR_HIP (launch failure).
+ */
+int tc_permute(const void* src, void* dst, int ndim, const int64_t* lens, const int64_t* src_strides,
+               const int64_t* dst_strides, int dtype, void* stream);
+
 const char* tc_status_string(int status);
 const char* tc_last_error(void);
 

@@ -799,6 +799,42 @@ int tc_block_strides(const int64_t* scat, int64_t len, int64_t b, int64_t* out) 
     return TC_OK;
 }
 
+int tc_permute(const void* src, void* dst, int ndim, const int64_t* lens, const int64_t* src_strides,
+               const int64_t* dst_strides, int dtype, void* stream) {
+    if (ndim < 0 || ndim > TC_MAX_NDIM) {
+        set_error("ndim outside [0, 16]");
+        return TC_ERR_NDIM;
+    }
+    if (ndim && (!lens || !src_strides || !dst_strides)) {
+        set_error("NULL descriptor array");
+        return TC_ERR_NULL;
+    }
+    if (dtype != TC_F64 && dtype != TC_F32) {
+        set_error("dtype must be TC_F64 or TC_F32");
+        return TC_ERR_DTYPE;
+    }
+    bool empty = false;
+    for (int d = 0; d < ndim; ++d) {
+        if (lens[d] < 0) {
+            set_error("negative length");
+            return TC_ERR_EXTENT;
+        }
+        if (lens[d] == 0) empty = true;
+    }
+    if (empty) return TC_OK;
+    for (int d = 0; d < ndim; ++d) {
+        if (lens[d] > 1 && (src_strides[d] <= 0 || dst_strides[d] <= 0)) {
+            set_error("stride <= 0 on a dimension of length > 1");
+            return TC_ERR_STRIDE;
+        }
+    }
+    if (!src || !dst) {
+        set_error("NULL data pointer");
+        return TC_ERR_NULL;
+    }
+    return launch_permute(src, dst, ndim, lens, src_strides, dst_strides, dtype, (hipStream_t)stream);
+}
+
 const char* tc_status_string(int status) {
     switch (status) {
         case TC_OK: return "ok";

@@ -44,4 +44,9 @@ int launch_batch(int dtype, int mode, int tile, bool off64, const BatchItemDev* 
 // workgroups of the tile's kernel on the current device).
 int batch_grid(int dtype, int mode, int tile, bool off64, int64_t total_items);
 
+// Strided permute-copy dst[i] = src[i] (element bits copied) on `stream`.
+// Arguments already validated by tc_permute.
+int launch_permute(const void* src, void* dst, int ndim, const int64_t* lens, const int64_t* src_strides,
+                   const int64_t* dst_strides, int dtype, hipStream_t stream);
+
 }  // namespace tc

@@ -22,7 +22,7 @@ EXPORTS = [
     "tc_plan_describe", "tc_tile_count", "tc_tile_info", "tc_plan_set_tile", "tc_plan_get_tile",
     "tc_plan_autotune", "tc_batch_create", "tc_batch_execute", "tc_batch_destroy", "tc_batch_info",
     "tc_batch_set_tile", "tc_batch_autotune",
-    "tc_scatter_vector", "tc_block_strides", "tc_status_string", "tc_last_error",
+    "tc_scatter_vector", "tc_block_strides", "tc_permute", "tc_status_string", "tc_last_error",
 ]
 
 
@@ -68,6 +68,7 @@ def lib():
         L.tc_batch_autotune.argtypes = [_vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double)]
         L.tc_scatter_vector.argtypes = [ctypes.c_int, _i64p, _i64p, _i64p]
         L.tc_block_strides.argtypes = [_i64p, ctypes.c_int64, ctypes.c_int64, _i64p]
+        L.tc_permute.argtypes = [_vp, _vp, ctypes.c_int, _i64p, _i64p, _i64p, ctypes.c_int, _vp]
         L.tc_status_string.argtypes = [ctypes.c_int]
         L.tc_status_string.restype = ctypes.c_char_p
         L.tc_last_error.argtypes = []
@@ -312,3 +313,105 @@ def describe(A_shape, A_strides, idx_A, B_shape, B_strides, idx_B, C_shape, C_st
         return p.describe()
     finally:
         p.close()
+
+
+def permute_into(src, dst, stream=None):
+    """dst[...] = src[...] elementwise (same shape, any strides) through the
+    library's permute-copy kernel; returns dst."""
+    if tuple(src.shape) != tuple(dst.shape) or src.dtype != dst.dtype:
+        raise ValueError("src and dst must have one shape and one dtype")
+    n = len(src.shape)
+    _check(lib().tc_permute(_ptr(src), _ptr(dst), n, _arr(src.shape), _arr(src.stride()), _arr(dst.stride()),
+                            _dtype_code(src.dtype), _stream_ptr(stream)))
+    return dst
+
+
+def _colmajor_strides(labels, ext):
+    out, s = {}, 1
+    for l in labels:
+        out[l] = s
+        s *= max(ext[l], 1)
+    return out
+
+
+class TTGT:
+    """The transpose-transpose-GEMM-transpose method (Sec. 3.2) on the GPU,
+    as the baseline the transpose-free contraction is measured against.
+
+    A is copied into a column-major m x k matrix (rows I, columns P), B into a
+    k x n matrix (P, J) and, when beta != 0, C into an m x n matrix (I, J), with
+    the library's permute-copy kernel; one plain matrix product then runs on
+    the linearised operands (the same contraction kernels, two-dimensional
+    descriptors), and the m x n result is copied back into C's layout.  I and
+    J are ordered as in C, P as in A.  The three matrices are the method's
+    extra workspace, allocated once here.
+    """
+
+    def __init__(self, A, idx_A, B, idx_B, C, idx_C, alpha=1.0, beta=0.0):
+        import torch
+        self.A, self.B, self.C = A, B, C
+        self.alpha, self.beta = float(alpha), float(beta)
+        ext = {}
+        for t, lab in ((A, idx_A), (B, idx_B), (C, idx_C)):
+            for l, n in zip(lab, t.shape):
+                ext[l] = n
+        I = [l for l in idx_C if l in idx_A]
+        J = [l for l in idx_C if l in idx_B]
+        P = [l for l in idx_A if l in idx_B]
+
+        def prod(ls):
+            r = 1
+            for l in ls:
+                r *= ext[l]
+            return r
+        self.m, self.n, self.k = prod(I), prod(J), prod(P)
+        m, n, k = self.m, self.n, self.k
+        dt, dv = A.dtype, A.device
+        self.Am = torch.empty(m * k, dtype=dt, device=dv)
+        self.Bm = torch.empty(k * n, dtype=dt, device=dv)
+        self.Cm = torch.empty(m * n, dtype=dt, device=dv)
+        sA = _colmajor_strides(I + P, ext)
+        sB = _colmajor_strides(P + J, ext)
+        sC = _colmajor_strides(I + J, ext)
+        # the matrices seen with each tensor's own index order
+        self.Av = torch.as_strided(self.Am, tuple(A.shape), [sA[l] for l in idx_A])
+        self.Bv = torch.as_strided(self.Bm, tuple(B.shape), [sB[l] for l in idx_B])
+        self.Cv = torch.as_strided(self.Cm, tuple(C.shape), [sC[l] for l in idx_C])
+        self.A2 = torch.as_strided(self.Am, (m, k), (1, m))
+        self.B2 = torch.as_strided(self.Bm, (k, n), (1, k))
+        self.C2 = torch.as_strided(self.Cm, (m, n), (1, m))
+        self.gemm_plan = Plan.for_tensors(self.A2, "ip", self.B2, "pj", self.C2, "ij")
+        self.gemm_plan.upload()
+
+    def workspace_bytes(self):
+        return (self.Am.numel() + self.Bm.numel() + self.Cm.numel()) * self.Am.element_size()
+
+    def transpose_in(self, stream=None):
+        permute_into(self.A, self.Av, stream)
+        permute_into(self.B, self.Bv, stream)
+        if self.beta != 0.0:
+            permute_into(self.C, self.Cv, stream)
+
+    def gemm(self, stream=None):
+        self.gemm_plan.execute(self.A2, self.B2, self.C2, self.alpha, self.beta, stream)
+
+    def transpose_out(self, stream=None):
+        permute_into(self.Cv, self.C, stream)
+
+    def run(self, stream=None):
+        self.transpose_in(stream)
+        self.gemm(stream)
+        self.transpose_out(stream)
+        return self.C
+
+    def close(self):
+        self.gemm_plan.close()
+
+
+def ttgt(A, idx_A, B, idx_B, C, idx_C, alpha=1.0, beta=0.0, stream=None):
+    """C[idx_C] = alpha A . B + beta C by transpose-transpose-GEMM-transpose."""
+    t = TTGT(A, idx_A, B, idx_B, C, idx_C, alpha, beta)
+    try:
+        return t.run(stream)
+    finally:
+        t.close()

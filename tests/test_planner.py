@@ -259,3 +259,20 @@ def test_describe_without_gpu_and_vectors_size_limit():
     big = inputs.Problem("ip", "pj", "ij", inputs.colmajor((8192, 2)), inputs.colmajor((2, 3)),
                          inputs.colmajor((8192, 3)))
     assert describe(big)["vectors"] is False
+
+
+def test_permute_abi_errors():
+    """tc_permute rejects bad descriptors on the host, before any launch."""
+    L = tc.lib()
+    lens = tc._arr([3, 4])
+    ss = tc._arr([1, 3])
+    ds = tc._arr([4, 1])
+    assert L.tc_permute(None, None, 17, lens, ss, ds, tc.TC_F64, None) == -2
+    assert L.tc_permute(None, None, 2, None, ss, ds, tc.TC_F64, None) == -1
+    assert L.tc_permute(None, None, 2, lens, ss, ds, 9, None) == -7
+    assert L.tc_permute(None, None, 2, tc._arr([3, -1]), ss, ds, tc.TC_F64, None) == -4
+    assert L.tc_permute(None, None, 2, lens, tc._arr([1, 0]), ds, tc.TC_F64, None) == -5
+    assert L.tc_permute(None, None, 2, lens, ss, tc._arr([-4, 1]), tc.TC_F32, None) == -5
+    assert L.tc_permute(None, None, 2, lens, ss, ds, tc.TC_F64, None) == -1  # NULL data, non-empty
+    # an empty index space is a no-op and needs no data
+    assert L.tc_permute(None, None, 2, tc._arr([3, 0]), ss, ds, tc.TC_F64, None) == 0
