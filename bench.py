@@ -97,6 +97,11 @@ def dev(a, dtype=None):
     return t
 
 
+def progress(msg):
+    """One line on stderr when a section of the benchmark has finished."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def time_calls(fn, steps, warmup):
     """Mean milliseconds per call, hipEvent timing on the current stream."""
     import torch
@@ -147,6 +152,7 @@ def secondary(tc, inputs, steps, warmup, quick):
             out[key]["note"] = "frac counts the three bf16 products (3 * 2mnk) against the dense bf16 peak"
         plan.close()
     del A, B, C
+    progress("FP32 and split-BF16 at v=96/o=24 done")
     # FP32 forward + backward, C[ijab] = A[iklb] B[kjal]
     p = inputs.cfg4()
     A, B, dC = dev(p.A, np.float32), dev(p.B, np.float32), dev(p.dC, np.float32)
@@ -181,6 +187,7 @@ def secondary(tc, inputs, steps, warmup, quick):
     ms = time_calls(fb, max(steps // 2, 3), 2)
     rec["autograd_fwd_bwd"] = {"gflops": round(3 * fl4 / ms / 1e6, 1), "ms": round(ms, 4)}
     out["fp32_fwd_bwd_ijab_iklb_kjal"] = rec
+    progress("FP32 forward + backward done")
     del A, B, C, dA, dB, dC, Ag, Bg
     # FP64 extent-16 contraction (latency-bound)
     p = inputs.cfg1()
@@ -192,7 +199,9 @@ def secondary(tc, inputs, steps, warmup, quick):
     del A, B, C
     if not quick:
         out["ttgt_baseline"] = ttgt_baseline(tc, inputs, steps, warmup)
+        progress("TTGT baseline done")
         out["batched_512_fp64"] = batched(tc, inputs, steps, warmup)
+        progress("batched 512 done")
         out["random_sweep_fp64"] = sweep(tc, inputs, max(steps // 2, 5), 2)
     torch.cuda.empty_cache()
     return out
@@ -271,6 +280,7 @@ def sweep(tc, inputs, steps, warmup, square=(512, 1024, 2048, 4096), rankk=(8, 3
             fast_c.append(d["c_tiles_regular"] / max(d["tiles_m"] * d["tiles_n"], 1))
             kb = max(d["k_blocks"], 1)
             fast_k.append(min(d["k_blocks_regular_x"], d["k_blocks_regular_y"]) / kb)
+        progress(f"sweep {kind} {m0}x{n0}x{k0} done")
         rows.append({"kind": kind, "target_mnk": [m0, n0, k0], "instances": seeds,
                      "gflops_mean": round(float(np.mean(rates)), 1), "gflops_min": round(float(np.min(rates)), 1),
                      "gemm_gflops_mean": round(float(np.mean(gemm_rates)), 1),
