@@ -329,8 +329,10 @@ def batched(tc, inputs, steps, warmup):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    # 100 untimed launches bring the matrix cores to their sustained clock
+    # (5 left the first timed launches measurably slower)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline workload only (no secondary workloads)")
     ap.add_argument("--tile", type=int, default=None, help="force a tile configuration")
