@@ -1,6 +1,7 @@
 """Benchmark of the transpose-free contraction on one GPU.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick] [--tile T] [--copy-calibration]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick] [--sections S] [--tile T]
+                 [--copy-calibration]
 
 Headline workload (value, roofline): the FP64 forward of the coupled-cluster
 shaped contraction Z[abij] = sum_{k,c} W[akic] T[cbkj] + Z with a,b,c = 96 and
@@ -14,7 +15,7 @@ contraction C[abcd] = A[aebf] B[dfce], 512 batched FP64 contractions against
 512 sequential launches, the transpose-transpose-GEMM-transpose method
 (Sec. 3.2) on the same GPU at the v=96/o=24 and the FP32 forward shapes, and a
 sweep of random contractions (Sec. 9.2) against plain GEMMs of the same size
-(unless --quick).
+(unless --quick; --sections fp32,fwdbwd,x16,ttgt,batched,sweep picks a subset).
 
   --copy-calibration first runs a plain 1 GiB device copy three times in the
   same process: the reference that scales rocprofv3's HBM byte counters.
@@ -132,9 +133,31 @@ def plan_runner(tc, A, ia, B, ib, C, ic, alpha, beta, mode="native"):
     return plan, run
 
 
-def secondary(tc, inputs, steps, warmup, quick):
+SECTIONS = ("fp32", "fwdbwd", "x16", "ttgt", "batched", "sweep")
+
+
+def secondary(tc, inputs, steps, warmup, sections=SECTIONS):
     import torch
     out = {}
+    if "fp32" in sections:
+        _fp32(tc, inputs, steps, warmup, out)
+    if "fwdbwd" in sections:
+        _fwdbwd(tc, inputs, steps, warmup, out)
+    if "x16" in sections:
+        _x16(tc, inputs, steps, warmup, out)
+    if "ttgt" in sections:
+        out["ttgt_baseline"] = ttgt_baseline(tc, inputs, steps, warmup)
+        progress("TTGT baseline done")
+    if "batched" in sections:
+        out["batched_512_fp64"] = batched(tc, inputs, steps, warmup)
+        progress("batched 512 done")
+    if "sweep" in sections:
+        out["random_sweep_fp64"] = sweep(tc, inputs, max(steps // 2, 5), 2)
+    torch.cuda.empty_cache()
+    return out
+
+
+def _fp32(tc, inputs, steps, warmup, out):
     # FP32 and split-BF16 at the v=96/o=24 shape
     p = inputs.cfg2()
     m, n, k = p.mnk()
@@ -153,6 +176,9 @@ def secondary(tc, inputs, steps, warmup, quick):
         plan.close()
     del A, B, C
     progress("FP32 and split-BF16 at v=96/o=24 done")
+
+
+def _fwdbwd(tc, inputs, steps, warmup, out):
     # FP32 forward + backward, C[ijab] = A[iklb] B[kjal]
     p = inputs.cfg4()
     A, B, dC = dev(p.A, np.float32), dev(p.B, np.float32), dev(p.dC, np.float32)
@@ -189,6 +215,9 @@ def secondary(tc, inputs, steps, warmup, quick):
     out["fp32_fwd_bwd_ijab_iklb_kjal"] = rec
     progress("FP32 forward + backward done")
     del A, B, C, dA, dB, dC, Ag, Bg
+
+
+def _x16(tc, inputs, steps, warmup, out):
     # FP64 extent-16 contraction (latency-bound)
     p = inputs.cfg1()
     A, B, C = dev(p.A), dev(p.B), dev(p.C)
@@ -197,14 +226,6 @@ def secondary(tc, inputs, steps, warmup, quick):
     out["fp64_abcd_aebf_dfce_x16"] = {"us_per_call": round(ms * 1e3, 2), "gflops": round(p.flops() / ms / 1e6, 1)}
     plan.close()
     del A, B, C
-    if not quick:
-        out["ttgt_baseline"] = ttgt_baseline(tc, inputs, steps, warmup)
-        progress("TTGT baseline done")
-        out["batched_512_fp64"] = batched(tc, inputs, steps, warmup)
-        progress("batched 512 done")
-        out["random_sweep_fp64"] = sweep(tc, inputs, max(steps // 2, 5), 2)
-    torch.cuda.empty_cache()
-    return out
 
 
 def ttgt_baseline(tc, inputs, steps, warmup):
@@ -335,11 +356,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline workload only (no secondary workloads)")
+    ap.add_argument("--sections", default=",".join(SECTIONS),
+                    help="comma-separated secondary workloads to run after the headline: " + ",".join(SECTIONS))
     ap.add_argument("--tile", type=int, default=None, help="force a tile configuration")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy three times (the reference for HBM byte "
                          "counters, taken in the same process as the contraction)")
     args = ap.parse_args()
+    sections = [x for x in args.sections.split(",") if x]
+    bad = [x for x in sections if x not in SECTIONS]
+    if bad:
+        print(f"bench.py: unknown section(s) {bad}; choose from {list(SECTIONS)}", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
@@ -399,7 +427,7 @@ def main():
         "wall_s_timed_region": round(wall, 3),
     }
     if not args.quick:
-        line["secondary"] = secondary(tc, inputs, max(args.steps // 2, 10), max(args.warmup, 5), False)
+        line["secondary"] = secondary(tc, inputs, max(args.steps // 2, 10), max(args.warmup, 5), sections)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(line), flush=True)
