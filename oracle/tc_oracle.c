@@ -16,7 +16,9 @@
  * where f runs over the labels of C and p over the labels shared by A and B.
  * Readings of points the paper leaves open:
  *   - beta == 0 means C is write-only (its old contents, NaN or not, are not
- *     read); alpha == 0 still evaluates the sum here (it is 0 * finite).
+ *     read); alpha == 0 means A and B are not read at all and C := beta * C
+ *     (the BLAS convention for the alpha/beta update of Sec. 3), so NaN or
+ *     Inf in A or B do not reach C when alpha == 0.
  *   - a label must appear in exactly two of the three tensors, once each, with
  *     equal extents; anything else is rejected (no trace / batch indices).
  *   - the sum over p runs over every p in colexicographic order (first label
@@ -161,6 +163,11 @@ static double update(double alpha, double sum, double beta, double c0) {
     return r;
 }
 
+/* alpha == 0: the sum is not formed (A and B unread); C := beta * C. */
+static double scale_only(double beta, double c0) {
+    return beta != 0.0 ? beta * c0 : 0.0;
+}
+
 /*
  * Full contraction into C (host arrays, strides in elements).
  * Parity pinned in the test suite against: numpy.einsum, an explicit
@@ -179,7 +186,7 @@ int oracle_contract(double alpha,
     if (st != ORC_OK) return st;
     int64_t nF = count_of(pr.nf, pr.flen);
     if (nF == 0) return ORC_OK;
-    if (!C || (count_of(pr.np, pr.plen) > 0 && (!A || !B))) return ORC_ERR_NULL;
+    if (!C || (alpha != 0.0 && count_of(pr.np, pr.plen) > 0 && (!A || !B))) return ORC_ERR_NULL;
     (void)nthreads;
 #pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads > 0 ? nthreads : 1)
     for (int64_t lin = 0; lin < nF; ++lin) {
@@ -190,6 +197,10 @@ int oracle_contract(double alpha,
             offC += f[i] * pr.fsC[i];
             baseA += f[i] * pr.fsA[i];
             baseB += f[i] * pr.fsB[i];
+        }
+        if (alpha == 0.0) {
+            C[offC] = scale_only(beta, beta != 0.0 ? C[offC] : 0.0);
+            continue;
         }
         double s = contracted_sum(&pr, A, B, baseA, baseB, absval);
         C[offC] = update(alpha, s, beta, beta != 0.0 ? C[offC] : 0.0);
@@ -224,8 +235,13 @@ int oracle_contract_points(double alpha,
             baseA += f[i] * pr.fsA[i];
             baseB += f[i] * pr.fsB[i];
         }
+        const double c0 = (beta != 0.0 && C) ? C[offC] : 0.0;
+        if (alpha == 0.0) {
+            out[q] = scale_only(beta, c0);
+            continue;
+        }
         double s = contracted_sum(&pr, A, B, baseA, baseB, absval);
-        out[q] = update(alpha, s, beta, (beta != 0.0 && C) ? C[offC] : 0.0);
+        out[q] = update(alpha, s, beta, c0);
     }
     return ORC_OK;
 }

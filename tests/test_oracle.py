@@ -219,6 +219,26 @@ def test_alpha_beta_semantics(oracle_mod):
     assert np.array_equal(run_oracle(oracle_mod, q), 0.5 * q.C)
 
 
+def test_alpha_zero_reads_neither_operand(oracle_mod):
+    """alpha = 0 (Sec. 3 alpha/beta update, read with the BLAS convention):
+    C := beta * C exactly, and NaN or Inf in A or B never reach C; with
+    beta = 0 as well, C := 0 whatever it held."""
+    p = inputs.random_problem(62, 2, 2, 2, lo=2, hi=5, beta=1.0)
+    A = np.array(p.A, order="F", copy=True)
+    B = np.array(p.B, order="F", copy=True)
+    A.reshape(-1, order="F")[::3] = np.nan
+    B.reshape(-1, order="F")[1::4] = np.inf
+    C0 = np.asfortranarray(np.random.default_rng(2).uniform(-1, 1, p.C.shape))
+    q = inputs.Problem(p.idx_A, p.idx_B, p.idx_C, A, B, C0, 0.0, -1.5)
+    assert np.array_equal(run_oracle(oracle_mod, q), -1.5 * C0)
+    pts = np.array(list(np.ndindex(*C0.shape)), dtype=np.int64)
+    vals = oracle_mod.contract_points(0.0, A, p.idx_A, B, p.idx_B, -1.5, C0, p.idx_C, pts)
+    assert np.array_equal(vals, np.array([-1.5 * C0[tuple(t)] for t in pts]))
+    Cn = np.full(C0.shape, np.nan, order="F")
+    q = inputs.Problem(p.idx_A, p.idx_B, p.idx_C, A, B, Cn, 0.0, 0.0)
+    assert np.array_equal(run_oracle(oracle_mod, q), np.zeros(C0.shape))
+
+
 def test_absval_variant(oracle_mod):
     p = inputs.random_problem(71, 2, 2, 1, lo=2, hi=5)
     got = run_oracle(oracle_mod, p, absval=True)

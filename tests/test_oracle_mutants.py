@@ -1,6 +1,7 @@
 """Plant plausible mistakes in copies of the oracle source (on the CPU only)
 and check that the pins catch every one: a dropped term, a wrong sign, a wrong
-stride, a transposed operand index, a lost beta term."""
+stride, a transposed operand index, a lost beta term, an alpha = 0 update that
+still forms the sum or drops beta."""
 import ctypes
 import os
 import subprocess
@@ -19,6 +20,9 @@ MUTANTS = {
     "transposed_free_index": ("pr->fsA[pr->nf] = (a >= 0) ? strA[a] : 0;",
                               "pr->fsA[pr->nf] = (a >= 0) ? strA[ndA - 1 - a] : 0;"),
     "lost_beta": ("if (beta != 0.0) r = r + beta * c0;", "(void)c0;"),
+    "alpha_zero_still_sums": ("        if (alpha == 0.0) {\n            C[offC] = scale_only",
+                              "        if (alpha == 0.0 && 0) {\n            C[offC] = scale_only"),
+    "alpha_zero_drops_beta": ("return beta != 0.0 ? beta * c0 : 0.0;", "return c0;"),
 }
 
 
@@ -57,6 +61,13 @@ def pins_pass(lib):
         want = np.einsum(f"{p.idx_A},{p.idx_B}->{p.idx_C}", p.A, p.B, optimize=False) * p.alpha + p.beta * p.C
         if np.max(np.abs(call(lib, p) - want)) > 1e-12:
             return False
+    # alpha = 0: C := beta * C, with NaN in A never read
+    p = inputs.random_problem(510, 2, 2, 2, lo=2, hi=5, beta=0.5)
+    A = np.array(p.A, order="F", copy=True)
+    A.reshape(-1, order="F")[::2] = np.nan
+    q = inputs.Problem(p.idx_A, p.idx_B, p.idx_C, A, p.B, p.C, 0.0, -0.5)
+    if not np.array_equal(call(lib, q), -0.5 * p.C):
+        return False
     return True
 
 
