@@ -24,7 +24,11 @@
  *   - A, B, C are DEVICE pointers owned by the caller.  A and B are read only;
  *     C must not overlap itself (checked: sorted by stride, each stride must
  *     be >= the previous stride times the previous length) nor overlap A or B
- *     (checked by address ranges).
+ *     (checked by address ranges).  Outside graph capture every data pointer
+ *     the call will read or write is also checked to be memory of the
+ *     current device whose allocation holds the tensor's whole element span
+ *     (TC_ERR_ARG otherwise, e.g. for a host pointer), so that such a mistake
+ *     is reported instead of reaching a kernel.
  *   - beta == 0: C is write-only (NaN/Inf in C are not propagated).
  *     alpha == 0: A and B are not read; C := beta * C.
  *     A length-0 free index makes the call a no-op; a length-0 contracted
@@ -167,8 +171,10 @@ int tc_plan_autotune(tc_plan* plan, const void* A, const void* B, void* C_scratc
  * are only read during the call.  tc_batch_execute then issues one persistent
  * launch per tile class present (see tc_batch_info) whose workgroups walk a
  * flattened list of (problem, tile) work items; it makes no allocation and no
- * host-device copy, so it may be recorded in a hipGraph and replayed.  C_i
- * must not overlap each other.
+ * host-device copy, so it may be recorded in a hipGraph and replayed.  All
+ * problems run inside the same launches, so no C_i may overlap another C_j
+ * or an operand A_j, B_j that problem j reads (checked at creation by
+ * address ranges: TC_ERR_ALIAS).
  */
 int tc_batch_create(tc_batch** batch, int count, const tc_plan* const* plans, const double* alpha,
                     const void* const* A, const void* const* B, const double* beta, void* const* C);
@@ -186,6 +192,11 @@ int tc_batch_destroy(tc_batch* batch);
  * equal); the specialised-wave pinwheel (layout 2) sums its centre fragment
  * in another order. */
 int tc_batch_info(const tc_batch* batch, int64_t* work_items, int* tile, int* grid);
+/* The tile configuration problem `problem` (its index in tc_batch_create's
+ * arrays) runs with under the batch's current setting, or -1 when the problem
+ * launches no work (an empty free extent).  TC_ERR_ARG for an index out of
+ * range. */
+int tc_batch_problem_tile(const tc_batch* batch, int problem, int* tile);
 /* Set one tile configuration for the whole batch (any layout but the
  * all-compute pinwheel, layout 1), or -1 for per-problem classes; re-uploads
  * the work table (synchronous, not during capture). */
@@ -213,17 +224,19 @@ int tc_block_strides(const int64_t* scat, int64_t len, int64_t b, int64_t* out);
 
 /*
  * Strided permute-copy, the explicit transposition of the
- * transpose-transpose-GEMM-transpose method (Sec. 3.2) that the contraction
+ * transpose-transpose-GEMM-transpose method (Sec. 5, fig. TTGT) that the contraction
  * above avoids; it lets that method be timed on the same device.
  * dst[x . dst_strides] = src[x . src_strides] for every multi-index x over
  * lens (ndim dimensions, ndim in [0, TC_MAX_NDIM]; strides in elements, > 0 on
  * dimensions of length > 1).  src and dst are device pointers owned by the
  * caller, of the storage type `dtype` (TC_F64 or TC_F32); element bits are
  * copied unchanged.  dst must not overlap src, and distinct x must reach
- * distinct dst elements; neither is checked (as with memcpy).  Asynchronous on
- * `stream`; an empty index space is a no-op.  Errors: TC_ERR_NDIM,
- * TC_ERR_NULL, TC_ERR_DTYPE, TC_ERR_EXTENT (negative length), TC_ERR_STRIDE,
- * TC_ERR_HIP (launch failure).
+ * distinct dst elements; neither is checked (as with memcpy).  Outside graph
+ * capture both pointers are checked to be memory of the current device
+ * holding the whole element span.  Asynchronous on `stream`; an empty index
+ * space is a no-op.  Errors: TC_ERR_NDIM, TC_ERR_NULL, TC_ERR_DTYPE,
+ * TC_ERR_EXTENT (negative length), TC_ERR_STRIDE, TC_ERR_ARG (not device
+ * memory of the current device), TC_ERR_HIP (launch failure).
  */
 int tc_permute(const void* src, void* dst, int ndim, const int64_t* lens, const int64_t* src_strides,
                const int64_t* dst_strides, int dtype, void* stream);

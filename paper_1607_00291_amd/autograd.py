@@ -65,7 +65,11 @@ class Contract(torch.autograd.Function):
             dB = _colmajor_like(B.shape, B.dtype, B.device)
             tc.contract(A, idx_A, dC, idx_C, idx_B, alpha=alpha, beta=0.0, out=dB, mode=mode)
         if has_c0 and ctx.needs_input_grad[7]:
-            dC0 = dC * beta
+            # dC0 := beta * dC by the library: a copy of dC scaled by a call
+            # with alpha = 0, which reads neither operand (C := beta * C)
+            dC0 = _colmajor_like(dC.shape, dC.dtype, dC.device)
+            dC0.copy_(dC)
+            tc.contract(A, idx_A, B, idx_B, idx_C, alpha=0.0, beta=beta, out=dC0, mode=mode)
         return dA, None, dB, None, None, None, None, dC0, None
 
 

@@ -26,7 +26,8 @@ struct tc_batch {
     int dtype = 0, mode = 0, tile = -1, count = 0, device = 0, grid = 0;
     bool off64 = false;
     int64_t total_items = 0;
-    std::vector<tc::BatchItemDev> host;  // per problem (device pointers filled)
+    std::vector<tc::BatchItemDev> host;  // per problem that launches work (device pointers filled)
+    std::vector<int> host_of;            // per problem: its index in `host`, -1 for an empty problem
     std::vector<int> best;               // per problem: its own regular tile class
     std::vector<int> order;              // problem index of each table entry
     struct Segment {
@@ -146,6 +147,52 @@ static bool overlaps(const void* a, int64_t na, const void* b, int64_t nb, size_
     return a0 < b0 + nb * (int64_t)w && b0 < a0 + na * (int64_t)w;
 }
 
+// A tensor's data must be device memory of the current device, and its
+// element span must lie inside the allocation holding its first element: a
+// host pointer or a descriptor reaching past the buffer would otherwise take
+// the kernel to an invalid address.  Skipped under graph capture (no runtime
+// queries there; plans must have been checked and uploaded beforehand).
+static int check_device_span(const void* ptr, int64_t span, size_t w, const char* name) {
+    if (!ptr || span <= 0) return TC_OK;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hipfail(e, "hipGetDevice");
+    hipPointerAttribute_t at{};
+    e = hipPointerGetAttributes(&at, ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // do not leave the failed query for a later launch check
+        set_error(std::string(name) + " is not device memory (host pointer?)");
+        return TC_ERR_ARG;
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged) {
+        set_error(std::string(name) + " is not device memory (host pointer?)");
+        return TC_ERR_ARG;
+    }
+    if (at.device != dev) {
+        set_error(std::string(name) + " lives on device " + std::to_string(at.device) + ", not on the current device " +
+                  std::to_string(dev));
+        return TC_ERR_ARG;
+    }
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)ptr);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return TC_OK;  // no range information: the type and device checks stand
+    }
+    const uintptr_t b0 = (uintptr_t)base, p0 = (uintptr_t)ptr;
+    if ((uint64_t)span > (uint64_t)((b0 + size - p0) / w)) {
+        set_error(std::string(name) + ": the descriptor's element span reaches past the end of its allocation");
+        return TC_ERR_ARG;
+    }
+    return TC_OK;
+}
+
+static bool capturing(hipStream_t stream) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
 static int execute(const tc_plan* plan, double alpha, const void* A, const void* B, double beta, void* C,
                    hipStream_t stream) {
     const Plan& p = *plan->p;
@@ -165,8 +212,7 @@ static int execute(const tc_plan* plan, double alpha, const void* A, const void*
         return TC_ERR_ALIAS;
     }
     DeviceVectors* dv = nullptr;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+    if (capturing(stream)) {
         int dev = 0;
         hipGetDevice(&dev);
         if (dev < 0 || dev >= kMaxDevices || !p.dev[dev].bytes) {
@@ -175,8 +221,11 @@ static int execute(const tc_plan* plan, double alpha, const void* A, const void*
         }
         dv = &p.dev[dev];
     } else {
-        int st = ensure_uploaded(p, &dv);
-        if (st) return st;
+        int st;
+        if ((st = check_device_span(C, p.spanC, w, "C"))) return st;
+        if (reads_ab && ((st = check_device_span(A, p.spanA, w, "A")) || (st = check_device_span(B, p.spanB, w, "B"))))
+            return st;
+        if ((st = ensure_uploaded(p, &dv))) return st;
     }
     return launch_plan(p, *dv, alpha, A, B, beta, C, stream);
 }
@@ -508,6 +557,58 @@ static int batch_layout(tc_batch* b) {
     return TC_OK;
 }
 
+// Every problem of a batch runs inside the same persistent launches, so one
+// problem's output must not overlap any other problem's output, nor any
+// operand another problem reads (address ranges of the element spans).  The
+// outputs are sorted by start address: they are pairwise disjoint iff each
+// starts at or after the furthest end before it; an operand range then meets
+// an output iff the first output ending after the operand's start begins
+// before the operand's end.
+static int check_batch_aliasing(int count, const tc_plan* const* plans, const double* alpha, const void* const* A,
+                                const void* const* B, void* const* C, size_t elt) {
+    struct Range {
+        uintptr_t lo, hi;
+        int prob;
+    };
+    std::vector<Range> outs;
+    for (int i = 0; i < count; ++i) {
+        const Plan& p = *plans[i]->p;
+        if (p.noop || p.m == 0 || p.n == 0 || p.spanC <= 0) continue;
+        outs.push_back({(uintptr_t)C[i], (uintptr_t)C[i] + (uintptr_t)p.spanC * elt, i});
+    }
+    std::sort(outs.begin(), outs.end(), [](const Range& x, const Range& y) { return x.lo < y.lo; });
+    for (size_t e = 1; e < outs.size(); ++e) {
+        // outputs before e are disjoint and sorted, so e-1 ends furthest
+        if (outs[e].lo < outs[e - 1].hi) {
+            set_error("the outputs of batch problems " + std::to_string(outs[e - 1].prob) + " and " +
+                      std::to_string(outs[e].prob) + " overlap");
+            return TC_ERR_ALIAS;
+        }
+    }
+    auto meets_output = [&](const void* ptr, int64_t span, int* who) {
+        if (!ptr || span <= 0) return false;
+        const uintptr_t lo = (uintptr_t)ptr, hi = lo + (uintptr_t)span * elt;
+        // the first output whose end lies past lo (ends increase with starts)
+        auto it = std::upper_bound(outs.begin(), outs.end(), lo, [](uintptr_t v, const Range& r) { return v < r.hi; });
+        if (it != outs.end() && it->lo < hi) {
+            *who = it->prob;
+            return true;
+        }
+        return false;
+    };
+    for (int i = 0; i < count; ++i) {
+        const Plan& p = *plans[i]->p;
+        if (p.noop || p.m == 0 || p.n == 0 || p.k_empty || alpha[i] == 0.0) continue;
+        int who = -1;
+        if (meets_output(A[i], p.spanA, &who) || meets_output(B[i], p.spanB, &who)) {
+            set_error("an operand of batch problem " + std::to_string(i) + " overlaps the output of problem " +
+                      std::to_string(who));
+            return TC_ERR_ALIAS;
+        }
+    }
+    return TC_OK;
+}
+
 static int batch_create(tc_batch** out, int count, const tc_plan* const* plans, const double* alpha,
                         const void* const* A, const void* const* B, const double* beta, void* const* C) {
     if (!out) {
@@ -565,11 +666,25 @@ static int batch_create(tc_batch** out, int count, const tc_plan* const* plans, 
         total += al(p.rX.size()) + al(p.cX.size()) + al(p.rY.size()) + al(p.cY.size()) + al(p.rC.size()) +
                  al(p.cC.size()) + al(p.kbsX.size()) + al(p.kbsY.size());
     }
+    int st = check_batch_aliasing(count, plans, alpha, A, B, C, elt);
+    if (st) return st;
+    for (int i = 0; i < count; ++i) {
+        const Plan& p = *plans[i]->p;
+        if (p.noop || p.m == 0 || p.n == 0) continue;
+        const bool reads_ab = !(p.k_empty || alpha[i] == 0.0);
+        if ((st = check_device_span(C[i], p.spanC, elt, "C")) ||
+            (reads_ab && ((st = check_device_span(A[i], p.spanA, elt, "A")) ||
+                          (st = check_device_span(B[i], p.spanB, elt, "B"))))) {
+            set_error(std::string(last_error()) + " (batch problem " + std::to_string(i) + ")");
+            return st;
+        }
+    }
     auto b = std::make_unique<tc_batch>();
     b->dtype = dtype;
     b->mode = mode;
     b->count = count;
     b->off64 = off64;
+    b->host_of.assign((size_t)count, -1);
     hipGetDevice(&b->device);
     std::vector<char> host(std::max<size_t>(total, 1) * w, 0);
     if (total) {
@@ -619,6 +734,7 @@ static int batch_create(tc_batch** out, int count, const tc_plan* const* plans, 
         it.y_lanes_n = p.y_lanes_n;
         it.kregX = p.k_blocks_regular_x == (int64_t)p.kbsX.size();
         it.kregY = p.k_blocks_regular_y == (int64_t)p.kbsY.size();
+        b->host_of[i] = (int)b->host.size();
         b->host.push_back(it);
         b->best.push_back(choose_tile(p, true));  // layouts a batch runs
     }
@@ -630,7 +746,7 @@ static int batch_create(tc_batch** out, int count, const tc_plan* const* plans, 
         }
     }
     b->tile = -1;  // every problem with its own tile class until tuned
-    int st = batch_layout(b.get());
+    st = batch_layout(b.get());
     if (st) {
         tc_batch_destroy(b.release());
         return st;
@@ -762,6 +878,20 @@ int tc_batch_info(const tc_batch* batch, int64_t* work_items, int* tile, int* gr
     return TC_OK;
 }
 
+int tc_batch_problem_tile(const tc_batch* batch, int problem, int* tile) {
+    if (!batch || !tile) {
+        set_error("batch or tile out-pointer is NULL");
+        return TC_ERR_NULL;
+    }
+    if (problem < 0 || problem >= batch->count) {
+        set_error("problem index out of range");
+        return TC_ERR_ARG;
+    }
+    const int h = batch->host_of[(size_t)problem];
+    *tile = h < 0 ? -1 : (batch->tile >= 0 ? batch->tile : batch->best[(size_t)h]);
+    return TC_OK;
+}
+
 int tc_scatter_vector(int ndim, const int64_t* lens, const int64_t* strides, int64_t* out) {
     if (ndim < 0 || ndim > TC_MAX_NDIM) {
         set_error("ndim outside [0, 16]");
@@ -831,6 +961,16 @@ int tc_permute(const void* src, void* dst, int ndim, const int64_t* lens, const 
     if (!src || !dst) {
         set_error("NULL data pointer");
         return TC_ERR_NULL;
+    }
+    if (!capturing((hipStream_t)stream)) {
+        int64_t ss = 1, ds = 1;
+        for (int d = 0; d < ndim; ++d) {
+            ss += (lens[d] - 1) * (lens[d] > 1 ? src_strides[d] : 0);
+            ds += (lens[d] - 1) * (lens[d] > 1 ? dst_strides[d] : 0);
+        }
+        const size_t w = elt_size(dtype);
+        int st;
+        if ((st = check_device_span(src, ss, w, "src")) || (st = check_device_span(dst, ds, w, "dst"))) return st;
     }
     return launch_permute(src, dst, ndim, lens, src_strides, dst_strides, dtype, (hipStream_t)stream);
 }

@@ -1,6 +1,6 @@
 // Strided permute-copy dst[i] = src[i] over one index space with two stride
 // sets: the "transpose" step of the transpose-transpose-GEMM-transpose
-// (TTGT) method of Sec. 3.2, which the block-scatter-matrix contraction
+// (TTGT) method of Sec. 5 (fig. TTGT), which the block-scatter-matrix contraction
 // avoids.  It exists to measure that method on the same device.
 //
 // Bandwidth-bound.  Two dimensions are picked: `a`, the unit-stride (or

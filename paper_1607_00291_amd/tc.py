@@ -21,7 +21,7 @@ EXPORTS = [
     "tc_contract", "tc_plan_create", "tc_plan_upload", "tc_plan_execute", "tc_plan_destroy",
     "tc_plan_describe", "tc_tile_count", "tc_tile_info", "tc_plan_set_tile", "tc_plan_get_tile",
     "tc_plan_autotune", "tc_batch_create", "tc_batch_execute", "tc_batch_destroy", "tc_batch_info",
-    "tc_batch_set_tile", "tc_batch_autotune",
+    "tc_batch_set_tile", "tc_batch_autotune", "tc_batch_problem_tile",
     "tc_scatter_vector", "tc_block_strides", "tc_permute", "tc_status_string", "tc_last_error",
 ]
 
@@ -66,6 +66,7 @@ def lib():
         L.tc_batch_info.argtypes = [_vp, _i64p, ip, ip]
         L.tc_batch_set_tile.argtypes = [_vp, ctypes.c_int]
         L.tc_batch_autotune.argtypes = [_vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double)]
+        L.tc_batch_problem_tile.argtypes = [_vp, ctypes.c_int, ip]
         L.tc_scatter_vector.argtypes = [ctypes.c_int, _i64p, _i64p, _i64p]
         L.tc_block_strides.argtypes = [_i64p, ctypes.c_int64, ctypes.c_int64, _i64p]
         L.tc_permute.argtypes = [_vp, _vp, ctypes.c_int, _i64p, _i64p, _i64p, ctypes.c_int, _vp]
@@ -248,6 +249,12 @@ class Batch:
     def tile(self, t):
         _check(lib().tc_batch_set_tile(self._h, int(t)))
 
+    def problem_tile(self, i):
+        """Tile configuration problem i runs with (-1: it launches no work)."""
+        t = ctypes.c_int()
+        _check(lib().tc_batch_problem_tile(self._h, int(i), ctypes.byref(t)))
+        return t.value
+
     def autotune(self, reps=3, stream=None):
         best = ctypes.c_double()
         _check(lib().tc_batch_autotune(self._h, int(reps), _stream_ptr(stream), ctypes.byref(best)))
@@ -268,8 +275,16 @@ class Batch:
 
 
 def _ptr(t):
+    """Data pointer of a tensor on the current HIP device (None when empty).
+    A tensor anywhere else is refused before the library is called: its
+    address would be meaningless to the kernels."""
     if t is None:
         return None
+    if t.device.type != "cuda":
+        raise ValueError(f"tensor on {t.device}: the contraction needs tensors on the current HIP device")
+    import torch
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError(f"tensor on {t.device}, but the current HIP device is cuda:{torch.cuda.current_device()}")
     return t.data_ptr() if t.numel() else None
 
 
@@ -335,7 +350,7 @@ def _colmajor_strides(labels, ext):
 
 
 class TTGT:
-    """The transpose-transpose-GEMM-transpose method (Sec. 3.2) on the GPU,
+    """The transpose-transpose-GEMM-transpose method (Sec. 5, fig. TTGT) on the GPU,
     as the baseline the transpose-free contraction is measured against.
 
     A is copied into a column-major m x k matrix (rows I, columns P), B into a

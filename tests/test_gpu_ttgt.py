@@ -1,4 +1,4 @@
-"""GPU parity of the transpose-transpose-GEMM-transpose baseline (Sec. 3.2):
+"""GPU parity of the transpose-transpose-GEMM-transpose baseline (Sec. 5, fig. TTGT):
 the permute-copy kernel against the definition of a copy (bit-exact), and the
 whole TTGT contraction against the CPU oracle within the FP64 and FP32 bounds."""
 import itertools

@@ -276,3 +276,57 @@ def test_permute_abi_errors():
     assert L.tc_permute(None, None, 2, lens, ss, ds, tc.TC_F64, None) == -1  # NULL data, non-empty
     # an empty index space is a no-op and needs no data
     assert L.tc_permute(None, None, 2, tc._arr([3, 0]), ss, ds, tc.TC_F64, None) == 0
+
+
+def _batch_status(problems):
+    """tc_batch_create on fake device addresses: every check below fails on
+    the host before any HIP call is made."""
+    L = tc.lib()
+    plans = [tc.Plan(*desc) for desc, _ in problems]
+    n = len(problems)
+    hs = (ctypes.c_void_p * n)(*[p.handle for p in plans])
+    al = (ctypes.c_double * n)(*([1.0] * n))
+    be = (ctypes.c_double * n)(*([0.0] * n))
+    As = (ctypes.c_void_p * n)(*[ptrs[0] for _, ptrs in problems])
+    Bs = (ctypes.c_void_p * n)(*[ptrs[1] for _, ptrs in problems])
+    Cs = (ctypes.c_void_p * n)(*[ptrs[2] for _, ptrs in problems])
+    h = ctypes.c_void_p()
+    st = L.tc_batch_create(ctypes.byref(h), n, hs, al, As, Bs, be, Cs)
+    for p in plans:
+        p.close()
+    return st, L.tc_last_error().decode()
+
+
+def test_batch_rejects_cross_problem_aliasing():
+    """Outputs of two problems that overlap, and an operand of one problem
+    inside another problem's output, are refused (TC_ERR_ALIAS)."""
+    gemm = ((4, 3), (1, 4), "ip", (3, 5), (1, 3), "pj", (4, 5), (1, 4), "ij")  # C spans 20 doubles
+    base = 1 << 40
+    A0, B0, C0 = base, base + 4096, base + 8192
+    A1, B1 = base + 16384, base + 20480
+    st, msg = _batch_status([(gemm, (A0, B0, C0)), (gemm, (A1, B1, C0 + 8 * 19))])
+    assert st == -6 and "outputs" in msg
+    st, msg = _batch_status([(gemm, (A0, B0, C0)), (gemm, (C0 + 8 * 5, B1, base + 32768))])
+    assert st == -6 and "operand of batch problem 1" in msg
+    st, msg = _batch_status([(gemm, (A0, B0, C0)), (gemm, (A1, C0, base + 32768))])
+    assert st == -6
+
+
+def test_batch_problem_tile_abi_errors():
+    L = tc.lib()
+    t = ctypes.c_int()
+    assert L.tc_batch_problem_tile(None, 0, ctypes.byref(t)) == -1
+
+
+def test_binding_refuses_host_tensors():
+    """A CPU tensor never reaches the library: its host address would be
+    meaningless to the kernels."""
+    import pytest
+    import torch
+    A = torch.zeros(4, 3, dtype=torch.float64)
+    B = torch.zeros(3, 5, dtype=torch.float64)
+    C = torch.zeros(4, 5, dtype=torch.float64)
+    with pytest.raises(ValueError, match="current HIP device"):
+        tc.contract(A, "ip", B, "pj", "ij", out=C)
+    with pytest.raises(ValueError, match="current HIP device"):
+        tc.permute_into(A, torch.zeros(4, 3, dtype=torch.float64))
