@@ -1,19 +1,24 @@
 """Benchmark of the transpose-free contraction on one GPU.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick] [--sections S] [--tile T]
-                 [--copy-calibration]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--settle-ms S] [--no-cpu] [--quick] [--sections S]
+                 [--tile T] [--copy-calibration]
 
 Headline workload (value, roofline): the FP64 forward of the coupled-cluster
 shaped contraction Z[abij] = sum_{k,c} W[akic] T[cbkj] + Z with a,b,c = 96 and
 i,j,k = 24 (alpha = beta = 1), inputs resident in HBM.  A step is one full
-contraction (one kernel launch); value = 2mnk / mean step time.
+contraction (one kernel launch); value = 2mnk / mean step time over the K
+timed steps.  Before the W warm-up steps the same launch is repeated for
+--settle-ms of wall time (default 400) while the engine clock is sampled, so
+that the timed steps do not run while the clock ramps up from idle; the line
+reports the settle phase, the sampled clock, and the median, min and max of
+the per-launch times (hipEvents between consecutive launches).
 
 The same line carries, under "secondary", the other workloads measured on the
 same GPU: FP32 and split-BF16 at the same shape, the FP32 forward + backward of
 C[ijab] = A[iklb] B[kjal] (i,j,k,l = 32, a,b = 64), the FP64 extent-16
 contraction C[abcd] = A[aebf] B[dfce], 512 batched FP64 contractions against
 512 sequential launches, the transpose-transpose-GEMM-transpose method
-(Sec. 3.2) on the same GPU at the v=96/o=24 and the FP32 forward shapes, and a
+(Sec. 5, fig. TTGT) on the same GPU at the v=96/o=24 and the FP32 forward shapes, and a
 sweep of random contractions (Sec. 9.2) against plain GEMMs of the same size
 (unless --quick; --sections fp32,fwdbwd,x16,ttgt,batched,sweep picks a subset).
 
@@ -62,27 +67,44 @@ def load_traffic(workload_key):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(p, target_s=12.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, target_s=9.0):
     """The oracle timed on the host on a bounded sample of output elements
-    (each a full-length contracted sum), scaled to GFLOP/s."""
+    (each a full-length contracted sum), scaled to GFLOP/s: once on every core
+    this process may use (the reported value) and once on one thread."""
     import oracle
     threads = oracle.default_threads()
     K = p.mnk()[2]
     rng = np.random.default_rng(1234)
 
-    def run(npts):
+    def run(npts, nthr):
         pts = np.stack([rng.integers(0, n, npts) for n in p.C.shape], axis=1)
         t0 = time.perf_counter()
-        oracle.contract_points(p.alpha, p.A, p.idx_A, p.B, p.idx_B, p.beta, p.C, p.idx_C, pts, threads=threads)
+        oracle.contract_points(p.alpha, p.A, p.idx_A, p.B, p.idx_B, p.beta, p.C, p.idx_C, pts, threads=nthr)
         return time.perf_counter() - t0
 
-    n = 4096
-    t = run(n)
-    n2 = int(min(max(n * target_s / max(t, 1e-3), n), 20_000_000))
-    t2 = run(n2)
-    flops = 2.0 * K * n2
-    return {"value": round(flops / t2 / 1e9, 4), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n2} random output elements of Z, each a full K={K} FP64 sum ({t2:.1f} s)"}
+    def rate(nthr, probe):
+        t = run(probe, nthr)
+        n2 = int(min(max(probe * target_s / max(t, 1e-3), probe), 20_000_000))
+        t2 = run(n2, nthr)
+        return 2.0 * K * n2 / t2 / 1e9, n2, t2
+
+    g_all, n_all, t_all = rate(threads, 4096)
+    g_one, n_one, t_one = rate(1, 256)
+    return {"value": round(g_all, 4), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "single_thread_value": round(g_one, 4), "cpu_model": cpu_model(),
+            "sample": f"random output elements of Z, each a full K={K} FP64 sum: {n_all} on {threads} threads "
+                      f"({t_all:.1f} s), {n_one} on 1 thread ({t_one:.1f} s)"}
 
 
 def dev(a, dtype=None):
@@ -101,6 +123,71 @@ def dev(a, dtype=None):
 def progress(msg):
     """One line on stderr when a section of the benchmark has finished."""
     print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def sclk_reader():
+    """A function returning the current engine clock in MHz (the active level
+    of the DPM table in sysfs) or None where it cannot be read."""
+    import glob
+    paths = sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk"))
+
+    def read():
+        for path in paths:
+            try:
+                with open(path) as fh:
+                    for line in fh:
+                        if line.rstrip().endswith("*"):
+                            return int(line.split(":")[1].strip().split("Mhz")[0].split("MHz")[0])
+            except (OSError, ValueError, IndexError):
+                continue
+        return None
+    return read
+
+
+def time_launches(fn, steps, warmup, settle_ms=0.0):
+    """Per-launch times of `steps` back-to-back calls on the current stream,
+    from hipEvents recorded between consecutive launches, after an optional
+    clock-settle phase (calls repeated for `settle_ms` of wall time, the
+    engine clock sampled meanwhile) and `warmup` untimed calls.  Returns the
+    mean (first to last event over steps), median, min and max in ms."""
+    import threading
+    import torch
+    settle = {"launches": 0, "ms": 0.0, "sclk_mhz": []}
+    if settle_ms > 0:
+        read = sclk_reader()
+        samples, stop = [], threading.Event()
+
+        def sample():
+            while not stop.is_set():
+                v = read()
+                if v is not None:
+                    samples.append(v)
+                time.sleep(0.02)
+        th = threading.Thread(target=sample, daemon=True)
+        th.start()
+        t0 = time.perf_counter()
+        while (time.perf_counter() - t0) * 1e3 < settle_ms:
+            for _ in range(16):
+                fn()
+            settle["launches"] += 16
+            torch.cuda.synchronize()
+        settle["ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+        stop.set()
+        th.join()
+        settle["sclk_mhz"] = sorted(set(samples))
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(s)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(s)
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    return {"mean": ev[0].elapsed_time(ev[steps]) / steps, "median": float(np.median(per)),
+            "min": float(per.min()), "max": float(per.max()), "settle": settle}
 
 
 def time_calls(fn, steps, warmup):
@@ -229,7 +316,7 @@ def _x16(tc, inputs, steps, warmup, out):
 
 
 def ttgt_baseline(tc, inputs, steps, warmup):
-    """The transpose-transpose-GEMM-transpose method (Sec. 3.2) on the same
+    """The transpose-transpose-GEMM-transpose method (Sec. 5, fig. TTGT) on the same
     GPU: permute-copies into matrix layout, one matrix product of the same
     kernels, permute-copy back; against the transpose-free contraction."""
     import torch
@@ -359,6 +446,9 @@ def main():
     ap.add_argument("--sections", default=",".join(SECTIONS),
                     help="comma-separated secondary workloads to run after the headline: " + ",".join(SECTIONS))
     ap.add_argument("--tile", type=int, default=None, help="force a tile configuration")
+    ap.add_argument("--settle-ms", type=float, default=400.0,
+                    help="before the warm-up steps, repeat the headline launch for this long (wall time) so the "
+                         "engine clock has left its idle level; the clock is sampled meanwhile (0: off)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy three times (the reference for HBM byte "
                          "counters, taken in the same process as the contraction)")
@@ -397,10 +487,12 @@ def main():
         plan.upload()
     desc = plan.describe()
     t_wall = time.perf_counter()
-    ms = time_calls(run, args.steps, args.warmup)
+    tm = time_launches(run, args.steps, args.warmup, settle_ms=args.settle_ms)
     wall = time.perf_counter() - t_wall
+    ms = tm["mean"]
     gflops = flops / (ms * 1e-3) / 1e9
     achieved_tf = gflops / 1e3
+    sclk_after = sclk_reader()()
     plan.close()
     del W, T, Z
 
@@ -423,7 +515,11 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved_tf / PEAK_FP64_TFLOPS, 4),
                      "traffic": load_traffic(WORKLOAD), "algorithmic_flops_per_launch": flops,
-                     "mean_launch_ms": round(ms, 5)},
+                     "mean_launch_ms": round(ms, 5), "median_launch_ms": round(tm["median"], 5),
+                     "min_launch_ms": round(tm["min"], 5), "max_launch_ms": round(tm["max"], 5),
+                     "frac_at_median": round(flops / (tm["median"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)},
+        "clock": {"settle_launches": tm["settle"]["launches"], "settle_ms": tm["settle"]["ms"],
+                  "sclk_mhz_during_settle": tm["settle"]["sclk_mhz"], "sclk_mhz_after_timed": sclk_after},
         "wall_s_timed_region": round(wall, 3),
     }
     if not args.quick:

@@ -71,18 +71,17 @@ def test_sweep_instances(oracle_mod, shape):
         check_fp64(oracle_mod, p, gpu_result(p))
 
 
+@pytest.mark.parametrize("f", [2, 1])
 @pytest.mark.parametrize("ext", [1, 3, 17, 97])
-def test_ragged_extents_every_tile(oracle_mod, ext):
-    """Extents that leave ragged tiles in m, n and k, under every tile config."""
+def test_ragged_extents_every_tile(oracle_mod, ext, f):
+    """Extents that leave ragged tiles in m, n and k, under every tile config.
+    With f = 1 the contracted bundle is the single label e, whose k blocks all
+    share one block stride, so the kernels' per-tile byte-offset path runs
+    with a partial last k block."""
     from paper_1607_00291_amd import tc
-    rng = np.random.default_rng(ext)
-    e = {"a": ext, "b": 5, "c": ext + 2, "d": 3, "e": ext + 1, "f": 2}
-    A = inputs.colmajor_from_flat(rng.uniform(-1, 1, e["a"] * e["e"] * e["b"] * e["f"]), (e["a"], e["e"], e["b"], e["f"]))
-    B = inputs.colmajor_from_flat(rng.uniform(-1, 1, e["d"] * e["f"] * e["c"] * e["e"]), (e["d"], e["f"], e["c"], e["e"]))
-    C = inputs.colmajor_from_flat(rng.uniform(-1, 1, e["a"] * e["b"] * e["c"] * e["d"]), (e["a"], e["b"], e["c"], e["d"]))
-    p = inputs.Problem("aebf", "dfce", "abcd", A, B, C, 1.25, 0.5, f"ragged{ext}", e)
+    p = ragged_problem(ext, beta=0.5, f=f)
     for t in range(tc.tile_count(tc.TC_F64)):
-        print(f"case ragged ext={ext} tile={t}", flush=True)
+        print(f"case ragged ext={ext} f={f} tile={t}", flush=True)
         check_fp64(oracle_mod, p, gpu_result(p, tile=t))
 
 
@@ -210,31 +209,69 @@ def test_noncontiguous_views(oracle_mod):
     check_fp64(oracle_mod, p, gpu_result(p))
 
 
-def test_cfg2_full_size_sampled(oracle_mod):
+def test_cfg2_full_size_every_output(oracle_mod):
     """The v=96/o=24 coupled-cluster contraction at full size, in the launch
-    configuration the benchmark times: 4096 sampled outputs against the
-    oracle evaluated point by point, plus a property check on all outputs."""
+    configuration the benchmark times (the plan's own tile choice): every one
+    of the 5.3 M outputs against the oracle, within the FP64 bound."""
     torch = require_gpu()
     from paper_1607_00291_amd import tc
     p = inputs.cfg2()
-    print("case cfg2 full", flush=True)
     A, B, C = to_dev(p.A), to_dev(p.B), to_dev(p.C)
     plan = tc.Plan.for_tensors(A, p.idx_A, B, p.idx_B, C, p.idx_C)
+    d = plan.describe()
+    print(f"case cfg2 full, tile {d['MT']}x{d['NT']}x{d['KT']} waves {d['waves']}", flush=True)
     plan.execute(A, B, C, p.alpha, p.beta)
     torch.cuda.synchronize()
     got = to_host(C)
-    rng = np.random.default_rng(99)
-    pts = np.stack([rng.integers(0, n, 4096) for n in p.C.shape], axis=1)
-    ref = oracle_mod.contract_points(p.alpha, p.A, p.idx_A, p.B, p.idx_B, p.beta, p.C, p.idx_C, pts)
-    vals = got[tuple(pts.T)]
-    K = p.mnk()[2]
-    bound = fp64_bound(K, p.alpha, np.max(np.abs(p.A)), np.max(np.abs(p.B)), p.beta, np.max(np.abs(p.C)))
-    assert np.max(np.abs(vals - ref)) <= bound
-    # property on all outputs: C - Z0 equals the contraction, whose magnitude
-    # is bounded by K max|W| max|T|
-    assert np.all(np.isfinite(got))
-    assert np.max(np.abs(got - p.C)) <= K * np.max(np.abs(p.A)) * np.max(np.abs(p.B))
     plan.close()
+    err = check_fp64(oracle_mod, p, got)
+    print(f"cfg2 full: max|C - Cref| = {err:.3e} over {got.size} outputs", flush=True)
+
+
+def ragged_problem(ext, beta, f=2):
+    """Extents that leave ragged tiles in m, n and k (m = ext * 5,
+    n = (ext + 2) * 3, k = (ext + 1) * f), alpha = 1.25."""
+    rng = np.random.default_rng(ext)
+    e = {"a": ext, "b": 5, "c": ext + 2, "d": 3, "e": ext + 1, "f": f}
+    mk = lambda lab: inputs.colmajor_from_flat(rng.uniform(-1, 1, int(np.prod(inputs.shape_of(lab, e)))),
+                                               inputs.shape_of(lab, e))
+    A, B, C = mk("aebf"), mk("dfce"), mk("abcd")
+    return inputs.Problem("aebf", "dfce", "abcd", A, B, C, 1.25, beta, f"ragged{ext}", e)
+
+
+@pytest.mark.parametrize("f", [2, 1])
+@pytest.mark.parametrize("ext", [1, 3, 17, 97])
+def test_ragged_extents_every_tile_fp32(oracle_mod, ext, f):
+    """The FP32 kernels with 32-bit offsets at ragged m, n and k, beta != 0,
+    under every tile configuration (including the specialised-wave pinwheel
+    and its partial last k block), within the FP32 componentwise bound."""
+    from paper_1607_00291_amd import tc
+    p = ragged_problem(ext, beta=-0.75, f=f)
+    q = inputs.Problem(p.idx_A, p.idx_B, p.idx_C, *(np.asfortranarray(x.astype(np.float32).astype(np.float64))
+                                                      for x in (p.A, p.B, p.C)), p.alpha, p.beta, p.name, p.extents)
+    ref = oracle_result(oracle_mod, q)
+    absC = oracle_result(oracle_mod, inputs.Problem(q.idx_A, q.idx_B, q.idx_C, q.A, q.B,
+                                                    np.zeros_like(q.C, order="F"), 1.0, 0.0), absval=True)
+    bound = fp32_componentwise(q.mnk()[2], q.alpha, absC, q.beta, q.C)
+    for t in range(tc.tile_count(tc.TC_F32)):
+        print(f"case ragged fp32 ext={ext} f={f} tile={t}", flush=True)
+        got = gpu_result(q, np.float32, tile=t).astype(np.float64)
+        assert np.all(np.abs(got - ref) <= bound + 1e-30), f"tile {t}"
+
+
+def test_alpha_zero_with_nan_operands(oracle_mod):
+    """alpha = 0 reads neither A nor B: with NaN and Inf in both operands the
+    GPU result equals the oracle's C := beta * C exactly (FP64 and FP32)."""
+    p = inputs.random_problem(6002, 2, 2, 2, lo=3, hi=19, beta=-2.0, alpha=0.0)
+    p.A.reshape(-1, order="F")[::3] = np.nan
+    p.B.reshape(-1, order="F")[1::5] = np.inf
+    ref = oracle_result(oracle_mod, p)
+    print("case alpha=0 with NaN operands", flush=True)
+    assert not np.isnan(ref).any()
+    assert np.array_equal(gpu_result(p), ref)
+    q = inputs.Problem(p.idx_A, p.idx_B, p.idx_C, p.A, p.B,
+                       np.asfortranarray(p.C.astype(np.float32).astype(np.float64)), 0.0, -2.0, p.name, p.extents)
+    assert np.array_equal(gpu_result(q, np.float32).astype(np.float64), oracle_result(oracle_mod, q))
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
