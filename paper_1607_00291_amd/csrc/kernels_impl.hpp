@@ -524,15 +524,17 @@ struct PackRole {
     // element i relative to its block's first k offset is the same in every
     // block, so it is formed once per tile, in bytes (out of range past the
     // edge), and the k offsets of a block reach the loads as one scalar.
-    // tail: the elements that stay inside the last, partial block (bit i).
-    uint32_t tail = 0;
+    // tail: the elements that stay inside the last, partial block (bit i;
+    // one bit per element of a thread's share, so at most 64 elements).
+    static_assert(E <= 64, "the partial-block mask holds one bit per element");
+    uint64_t tail = 0;
     __device__ __forceinline__ void fix_offsets(OffT s, OffT K, int t) {
         const OffT rem = K % KT;
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const OffT kk = (OffT)kidx(t + NTHR * i);
             o[i] = o[i] >= 0 ? (OffT)((uint32_t)(o[i] + kk * s) * (uint32_t)sizeof(T)) : (OffT)kOutOfRange;
-            tail |= (uint32_t)(kk < rem) << i;
+            tail |= (uint64_t)(kk < rem) << i;
         }
     }
     // The same with the k block's stride and first k offset already in
@@ -552,7 +554,7 @@ struct PackRole {
             const bool partial = k0 + KT > K;
 #pragma unroll
             for (int i = 0; i < E; ++i) {
-                const uint32_t vo = partial && !((tail >> i) & 1u) ? kOutOfRange : (uint32_t)o[i];
+                const uint32_t vo = partial && !((tail >> i) & 1ull) ? kOutOfRange : (uint32_t)o[i];
                 r[SL][i] = buf_load<T>(rs, vo, soff);
             }
             return;
