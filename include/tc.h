@@ -95,6 +95,31 @@ int tc_contract(double alpha,
                 int dtype, int mode, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * contraction as tc_contract, with the same arguments, meaning and errors,
+ * but it allocates nothing on the device and copies nothing from the host.
+ * The plan is built on the host (and kept in a host-side cache), and its
+ * offset and block-stride vectors are written by a small kernel on `stream`
+ * into a static device array of TC_NOALLOC_SCRATCH_BYTES that each GPU the
+ * library runs on holds until the process ends; the contraction kernel then
+ * reads them from there.  A problem whose vectors need more than that
+ * (about 2 (m + n + k) offsets of 4 bytes, 8 with 64-bit offsets, each vector
+ * rounded up to 256 bytes) is refused with TC_ERR_ARG before any launch.
+ * Every call on a GPU reuses that GPU's array and it keeps the last call's
+ * contents: calls that may overlap in time on one GPU (other streams, other
+ * threads) race and must be serialised by the caller; calls on one stream
+ * are ordered.
+ */
+#define TC_NOALLOC_SCRATCH_BYTES (8u << 20)
+int tc_contract_noalloc(double alpha,
+                        const void* A, int ndim_A, const int64_t* lens_A, const int64_t* strides_A, const char* idx_A,
+                        const void* B, int ndim_B, const int64_t* lens_B, const int64_t* strides_B, const char* idx_B,
+                        double beta,
+                        void* C, int ndim_C, const int64_t* lens_C, const int64_t* strides_C, const char* idx_C,
+                        int dtype, int mode, void* stream);
+
+/*
  * Plan creation (host only; no GPU call).  Validates the descriptors (the
  * rules above), groups the labels into I, J, P (Sec. 4), orders them with the
  * reordering heuristic of Sec. 7.3 (drop length-1 dimensions; sort I and J by

@@ -77,7 +77,8 @@ static std::string desc_key(const TensorDesc& t) {
 
 // ---- plan cache and autotuner cache -------------------------------------
 static std::mutex g_cache_mu;
-static std::map<std::string, std::unique_ptr<tc_plan>> g_plans;
+static std::map<std::string, std::unique_ptr<tc_plan>> g_plans;       // tc_contract
+static std::map<std::string, std::unique_ptr<tc_plan>> g_host_plans;  // tc_contract_noalloc (never uploaded)
 static std::map<std::string, int> g_tuned;  // plan signature -> tile
 
 static size_t elt_size(int dtype) { return dtype == TC_F64 ? 8 : 4; }
@@ -193,9 +194,12 @@ static bool capturing(hipStream_t stream) {
     return hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
 }
 
-static int execute(const tc_plan* plan, double alpha, const void* A, const void* B, double beta, void* C,
-                   hipStream_t stream) {
-    const Plan& p = *plan->p;
+// Checks shared by every execution path: NULL data, C overlapping A or B,
+// and (outside capture) device memory holding each span.  *run = false when
+// the call is a no-op.
+static int check_call(const Plan& p, double alpha, const void* A, const void* B, void* C, hipStream_t stream,
+                      bool* run) {
+    *run = false;
     if (p.noop || p.m == 0 || p.n == 0) return TC_OK;
     if (!C) {
         set_error("C is NULL");
@@ -211,6 +215,22 @@ static int execute(const tc_plan* plan, double alpha, const void* A, const void*
         set_error("C overlaps A or B");
         return TC_ERR_ALIAS;
     }
+    if (!capturing(stream)) {
+        int st;
+        if ((st = check_device_span(C, p.spanC, w, "C"))) return st;
+        if (reads_ab && ((st = check_device_span(A, p.spanA, w, "A")) || (st = check_device_span(B, p.spanB, w, "B"))))
+            return st;
+    }
+    *run = true;
+    return TC_OK;
+}
+
+static int execute(const tc_plan* plan, double alpha, const void* A, const void* B, double beta, void* C,
+                   hipStream_t stream) {
+    const Plan& p = *plan->p;
+    bool run = false;
+    int st = check_call(p, alpha, A, B, C, stream, &run);
+    if (st || !run) return st;
     DeviceVectors* dv = nullptr;
     if (capturing(stream)) {
         int dev = 0;
@@ -220,12 +240,8 @@ static int execute(const tc_plan* plan, double alpha, const void* A, const void*
             return TC_ERR_CAPTURE;
         }
         dv = &p.dev[dev];
-    } else {
-        int st;
-        if ((st = check_device_span(C, p.spanC, w, "C"))) return st;
-        if (reads_ab && ((st = check_device_span(A, p.spanA, w, "A")) || (st = check_device_span(B, p.spanB, w, "B"))))
-            return st;
-        if ((st = ensure_uploaded(p, &dv))) return st;
+    } else if ((st = ensure_uploaded(p, &dv))) {
+        return st;
     }
     return launch_plan(p, *dv, alpha, A, B, beta, C, stream);
 }
@@ -253,6 +269,49 @@ static int create(tc_plan** out, int ndim_A, const int64_t* lens_A, const int64_
     }
     h->p = std::move(p);
     *out = h;
+    return TC_OK;
+}
+
+// The plan of a descriptor set from `cache` (created and inserted on first
+// use).  The one-shot entry points keep separate caches: tc_contract's plans
+// hold device copies of their vectors, the allocation-free path's never do.
+static int cached_plan(std::map<std::string, std::unique_ptr<tc_plan>>& cache, int ndim_A, const int64_t* lens_A,
+                       const int64_t* strides_A, const char* idx_A, int ndim_B, const int64_t* lens_B,
+                       const int64_t* strides_B, const char* idx_B, int ndim_C, const int64_t* lens_C,
+                       const int64_t* strides_C, const char* idx_C, int dtype, int mode, tc_plan** out) {
+    TensorDesc a, b, c;
+    int st;
+    if ((st = make_desc(ndim_A, lens_A, strides_A, idx_A, "A", &a)) ||
+        (st = make_desc(ndim_B, lens_B, strides_B, idx_B, "B", &b)) ||
+        (st = make_desc(ndim_C, lens_C, strides_C, idx_C, "C", &c)))
+        return st;
+    std::string key;
+    key.push_back((char)dtype);
+    key.push_back((char)mode);
+    key += desc_key(a);
+    key += desc_key(b);
+    key += desc_key(c);
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            *out = it->second.get();
+            return TC_OK;
+        }
+    }
+    tc_plan* fresh = nullptr;
+    if ((st = create(&fresh, ndim_A, lens_A, strides_A, idx_A, ndim_B, lens_B, strides_B, idx_B, ndim_C, lens_C,
+                     strides_C, idx_C, dtype, mode)))
+        return st;
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        *out = fresh;
+        cache[key].reset(fresh);
+    } else {
+        *out = it->second.get();
+        delete fresh;  // no device copies yet
+    }
     return TC_OK;
 }
 
@@ -434,40 +493,41 @@ int tc_contract(double alpha, const void* A, int ndim_A, const int64_t* lens_A, 
                 const char* idx_B, double beta, void* C, int ndim_C, const int64_t* lens_C, const int64_t* strides_C,
                 const char* idx_C, int dtype, int mode, void* stream) {
     try {
-        TensorDesc a, b, c;
-        int st;
-        if ((st = make_desc(ndim_A, lens_A, strides_A, idx_A, "A", &a)) ||
-            (st = make_desc(ndim_B, lens_B, strides_B, idx_B, "B", &b)) ||
-            (st = make_desc(ndim_C, lens_C, strides_C, idx_C, "C", &c)))
-            return st;
-        std::string key;
-        key.push_back((char)dtype);
-        key.push_back((char)mode);
-        key += desc_key(a);
-        key += desc_key(b);
-        key += desc_key(c);
         tc_plan* plan = nullptr;
-        {
-            std::lock_guard<std::mutex> g(g_cache_mu);
-            auto it = g_plans.find(key);
-            if (it != g_plans.end()) plan = it->second.get();
-        }
-        if (!plan) {
-            tc_plan* fresh = nullptr;
-            if ((st = create(&fresh, ndim_A, lens_A, strides_A, idx_A, ndim_B, lens_B, strides_B, idx_B, ndim_C,
-                             lens_C, strides_C, idx_C, dtype, mode)))
-                return st;
-            std::lock_guard<std::mutex> g(g_cache_mu);
-            auto it = g_plans.find(key);
-            if (it == g_plans.end()) {
-                plan = fresh;
-                g_plans[key].reset(fresh);
-            } else {
-                plan = it->second.get();
-                tc_plan_destroy(fresh);
-            }
-        }
+        int st = cached_plan(g_plans, ndim_A, lens_A, strides_A, idx_A, ndim_B, lens_B, strides_B, idx_B, ndim_C,
+                             lens_C, strides_C, idx_C, dtype, mode, &plan);
+        if (st) return st;
         return execute(plan, alpha, A, B, beta, C, (hipStream_t)stream);
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory");
+        return TC_ERR_NOMEM;
+    } catch (...) {
+        set_error("internal error");
+        return TC_ERR_ARG;
+    }
+}
+
+int tc_contract_noalloc(double alpha, const void* A, int ndim_A, const int64_t* lens_A, const int64_t* strides_A,
+                        const char* idx_A, const void* B, int ndim_B, const int64_t* lens_B, const int64_t* strides_B,
+                        const char* idx_B, double beta, void* C, int ndim_C, const int64_t* lens_C,
+                        const int64_t* strides_C, const char* idx_C, int dtype, int mode, void* stream) {
+    try {
+        tc_plan* plan = nullptr;
+        int st = cached_plan(g_host_plans, ndim_A, lens_A, strides_A, idx_A, ndim_B, lens_B, strides_B, idx_B, ndim_C,
+                             lens_C, strides_C, idx_C, dtype, mode, &plan);
+        if (st) return st;
+        const Plan& p = *plan->p;
+        DeviceVectors dv;
+        if (!p.noop && noalloc_layout(p, &dv) > (size_t)TC_NOALLOC_SCRATCH_BYTES) {
+            set_error("the plan's offset vectors need " + std::to_string(dv.bytes) +
+                      " bytes, more than the allocation-free entry point's array of " +
+                      std::to_string((long long)TC_NOALLOC_SCRATCH_BYTES) + " bytes");
+            return TC_ERR_ARG;
+        }
+        bool run = false;
+        if ((st = check_call(p, alpha, A, B, C, (hipStream_t)stream, &run)) || !run) return st;
+        if ((st = noalloc_vectors(p, (hipStream_t)stream, &dv))) return st;
+        return launch_plan(p, dv, alpha, A, B, beta, C, (hipStream_t)stream);
     } catch (const std::bad_alloc&) {
         set_error("out of host memory");
         return TC_ERR_NOMEM;

@@ -44,6 +44,12 @@ int launch_batch(int dtype, int mode, int tile, bool off64, const BatchItemDev* 
 // workgroups of the tile's kernel on the current device).
 int batch_grid(int dtype, int mode, int tile, bool off64, int64_t total_items);
 
+// Allocation-free execution (noalloc.hip): the byte size of a plan's vectors
+// laid out as in an upload (offsets into *dv), and a kernel writing them into
+// the current device's static array on `stream` (*dv then points there).
+size_t noalloc_layout(const Plan& p, DeviceVectors* dv);
+int noalloc_vectors(const Plan& p, hipStream_t stream, DeviceVectors* dv);
+
 // Strided permute-copy dst[i] = src[i] (element bits copied) on `stream`.
 // Arguments already validated by tc_permute.
 int launch_permute(const void* src, void* dst, int ndim, const int64_t* lens, const int64_t* src_strides,

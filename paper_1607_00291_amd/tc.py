@@ -18,7 +18,7 @@ MODES = {"native": TC_NATIVE, "split_bf16x3": TC_SPLIT_BF16X3, "split-bf16": TC_
 
 # every symbol include/tc.h declares
 EXPORTS = [
-    "tc_contract", "tc_plan_create", "tc_plan_upload", "tc_plan_execute", "tc_plan_destroy",
+    "tc_contract", "tc_contract_noalloc", "tc_plan_create", "tc_plan_upload", "tc_plan_execute", "tc_plan_destroy",
     "tc_plan_describe", "tc_tile_count", "tc_tile_info", "tc_plan_set_tile", "tc_plan_get_tile",
     "tc_plan_autotune", "tc_batch_create", "tc_batch_execute", "tc_batch_destroy", "tc_batch_info",
     "tc_batch_set_tile", "tc_batch_autotune", "tc_batch_problem_tile",
@@ -47,6 +47,7 @@ def lib():
         desc = [ctypes.c_int, _i64p, _i64p, ctypes.c_char_p]
         L.tc_contract.argtypes = ([ctypes.c_double, _vp] + desc + [_vp] + desc + [ctypes.c_double, _vp] + desc
                                   + [ctypes.c_int, ctypes.c_int, _vp])
+        L.tc_contract_noalloc.argtypes = L.tc_contract.argtypes
         L.tc_plan_create.argtypes = [ctypes.POINTER(_vp)] + desc * 3 + [ctypes.c_int, ctypes.c_int]
         L.tc_plan_upload.argtypes = [_vp]
         L.tc_plan_execute.argtypes = [_vp, ctypes.c_double, _vp, _vp, ctypes.c_double, _vp, _vp]
@@ -317,6 +318,21 @@ def contract(A, idx_A, B, idx_B, idx_C, alpha=1.0, beta=0.0, out=None, mode="nat
                              *_desc(tuple(B.shape), B.stride(), idx_B), float(beta), _ptr(out),
                              *_desc(tuple(out.shape), out.stride(), idx_C), _dtype_code(A.dtype), mode_code,
                              _stream_ptr(stream)))
+    return out
+
+
+def contract_noalloc(A, idx_A, B, idx_B, idx_C, out, alpha=1.0, beta=0.0, mode="native", stream=None):
+    """The same as ``contract`` with a given ``out``, through the entry point
+    that allocates no device memory (tc_contract_noalloc): for callers that
+    cannot allocate.  Calls that overlap in time on one GPU race on the
+    library's static array; serialise them.  Returns out."""
+    mode_code = MODES[mode] if isinstance(mode, str) else mode
+    if A.dtype != B.dtype or out.dtype != A.dtype:
+        raise TypeError("A, B and out must have one dtype")
+    _check(lib().tc_contract_noalloc(float(alpha), _ptr(A), *_desc(tuple(A.shape), A.stride(), idx_A), _ptr(B),
+                                     *_desc(tuple(B.shape), B.stride(), idx_B), float(beta), _ptr(out),
+                                     *_desc(tuple(out.shape), out.stride(), idx_C), _dtype_code(A.dtype), mode_code,
+                                     _stream_ptr(stream)))
     return out
 
 

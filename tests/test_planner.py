@@ -330,3 +330,17 @@ def test_binding_refuses_host_tensors():
         tc.contract(A, "ip", B, "pj", "ij", out=C)
     with pytest.raises(ValueError, match="current HIP device"):
         tc.permute_into(A, torch.zeros(4, 3, dtype=torch.float64))
+
+
+def test_noalloc_refuses_vectors_beyond_its_array():
+    """tc_contract_noalloc refuses, before any launch or HIP call, a problem
+    whose offset vectors exceed its static array (fake device addresses)."""
+    L = tc.lib()
+    m = (8 << 20) // 8 + 1024  # rscat_X and rscat_C alone pass 8 MiB of int32
+    shpA, stA = tc._arr([m, 2]), tc._arr([1, m])
+    shpB, stB = tc._arr([2, 3]), tc._arr([1, 2])
+    shpC, stC = tc._arr([m, 3]), tc._arr([1, m])
+    base = 1 << 40
+    st = L.tc_contract_noalloc(1.0, base, 2, shpA, stA, b"ip", base + (1 << 30), 2, shpB, stB, b"pj", 0.0,
+                               base + (1 << 31), 2, shpC, stC, b"ij", tc.TC_F64, tc.TC_NATIVE, None)
+    assert st == -10 and b"allocation-free" in L.tc_last_error()
