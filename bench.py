@@ -7,11 +7,14 @@ Headline workload (value, roofline): the FP64 forward of the coupled-cluster
 shaped contraction Z[abij] = sum_{k,c} W[akic] T[cbkj] + Z with a,b,c = 96 and
 i,j,k = 24 (alpha = beta = 1), inputs resident in HBM.  A step is one full
 contraction (one kernel launch); value = 2mnk / mean step time over the K
-timed steps.  Before the W warm-up steps the same launch is repeated for
---settle-ms of wall time (default 400) while the engine clock is sampled, so
-that the timed steps do not run while the clock ramps up from idle; the line
-reports the settle phase, the sampled clock, and the median, min and max of
-the per-launch times (hipEvents between consecutive launches).
+timed steps (two hipEvents around them).  Before the W warm-up steps the same
+launch is repeated for --settle-ms of wall time (default 400) while the engine
+clock is sampled, so that the timed steps do not run while the clock ramps up
+from idle (it needs about 20 ms of sustained load after any idle gap of a
+few milliseconds); the line reports the settle phase, the sampled clock, and
+the median, min and max of per-launch times from a pass of K launches with a
+hipEvent between consecutive launches, run between the warm-up and the timed
+steps.
 
 The same line carries, under "secondary", the other workloads measured on the
 same GPU: FP32 and split-BF16 at the same shape, the FP32 forward + backward of
@@ -145,17 +148,25 @@ def sclk_reader():
 
 
 def time_launches(fn, steps, warmup, settle_ms=0.0):
-    """Per-launch times of `steps` back-to-back calls on the current stream,
-    from hipEvents recorded between consecutive launches, after an optional
-    clock-settle phase (calls repeated for `settle_ms` of wall time, the
-    engine clock sampled meanwhile) and `warmup` untimed calls.  Returns the
-    mean (first to last event over steps), median, min and max in ms."""
+    """Time `steps` back-to-back calls on the current stream.
+
+    First, optionally, a clock-settle phase: calls repeated for `settle_ms`
+    of wall time (synchronising every 16 calls) while the engine clock is
+    sampled; the engine clock drops within milliseconds of the GPU going idle
+    and needs about 20 ms of sustained load to come back, so the phases below
+    follow it with no idle gap.  Then `warmup` untimed calls, a pass of
+    `steps` calls with a hipEvent between consecutive calls (per-launch
+    median, min and max; the events add a few microseconds between kernels),
+    and the timed pass: `steps` calls bracketed by two hipEvents, whose mean
+    is the reported time per step."""
     import threading
     import torch
     settle = {"launches": 0, "ms": 0.0, "sclk_mhz": []}
+    th = stop = None
+    samples = []
     if settle_ms > 0:
         read = sclk_reader()
-        samples, stop = [], threading.Event()
+        stop = threading.Event()
 
         def sample():
             while not stop.is_set():
@@ -172,29 +183,44 @@ def time_launches(fn, steps, warmup, settle_ms=0.0):
             settle["launches"] += 16
             torch.cuda.synchronize()
         settle["ms"] = round((time.perf_counter() - t0) * 1e3, 1)
-        stop.set()
-        th.join()
-        settle["sclk_mhz"] = sorted(set(samples))
+        stop.set()  # joined after the timed pass, so no idle gap here
     for _ in range(warmup):
         fn()
-    torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ev[0].record(s)
     for i in range(steps):
         fn()
         ev[i + 1].record(s)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    if th is not None:
+        th.join()
+        settle["sclk_mhz"] = sorted(set(samples))
     per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
-    return {"mean": ev[0].elapsed_time(ev[steps]) / steps, "median": float(np.median(per)),
+    return {"mean": e0.elapsed_time(e1) / steps, "median": float(np.median(per)),
             "min": float(per.min()), "max": float(per.max()), "settle": settle}
 
 
-def time_calls(fn, steps, warmup):
-    """Mean milliseconds per call, hipEvent timing on the current stream."""
+def time_calls(fn, steps, warmup, settle_ms=60.0):
+    """Mean milliseconds per call, hipEvent timing on the current stream,
+    after `warmup` untimed calls that continue (synchronising every 8 calls)
+    until `settle_ms` of wall time have passed, so that the engine clock is
+    back from idle when the timed calls start."""
     import torch
-    for _ in range(warmup):
+    t0 = time.perf_counter()
+    done = 0
+    while done < warmup or (time.perf_counter() - t0) * 1e3 < settle_ms:
         fn()
+        done += 1
+        if done % 8 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -517,9 +543,11 @@ def main():
                      "traffic": load_traffic(WORKLOAD), "algorithmic_flops_per_launch": flops,
                      "mean_launch_ms": round(ms, 5), "median_launch_ms": round(tm["median"], 5),
                      "min_launch_ms": round(tm["min"], 5), "max_launch_ms": round(tm["max"], 5),
-                     "frac_at_median": round(flops / (tm["median"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)},
+                     "frac_at_median": round(flops / (tm["median"] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+                     "per_launch_note": "median/min/max from a pass with a hipEvent between launches"},
         "clock": {"settle_launches": tm["settle"]["launches"], "settle_ms": tm["settle"]["ms"],
-                  "sclk_mhz_during_settle": tm["settle"]["sclk_mhz"], "sclk_mhz_after_timed": sclk_after},
+                  "sclk_mhz_sysfs_during_settle": tm["settle"]["sclk_mhz"], "sclk_mhz_sysfs_after_timed": sclk_after,
+                  "sclk_note": "active DPM level read from sysfs pp_dpm_sclk (a slowly averaged value)"},
         "wall_s_timed_region": round(wall, 3),
     }
     if not args.quick:

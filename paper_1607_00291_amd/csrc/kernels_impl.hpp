@@ -791,19 +791,23 @@ struct TilePinwheel8 {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// round-to-nearest-even FP32 -> bf16 bits; NaN stays NaN
-__device__ __forceinline__ uint32_t bf16_bits(float x) {
-    const uint32_t u = __builtin_bit_cast(uint32_t, x);
-    if (x != x) return 0x7fc0u;
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-__device__ __forceinline__ float bf16_value(uint32_t h) { return __builtin_bit_cast(float, h << 16); }
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-// hi and lo halves of x (lo = 0 when x is not finite)
-__device__ __forceinline__ void split_bf16(float x, uint32_t& hi, uint32_t& lo) {
-    hi = bf16_bits(x);
-    const float r = x - bf16_value(hi);
-    lo = (r == r && __builtin_fabsf(r) != __builtin_inff()) ? bf16_bits(r) : 0u;
+// hi and lo halves of a pair (x0, x1) as packed bf16 words (x0 in the low
+// half): hi = rn_bf16(x) by the hardware round-to-nearest-even conversion
+// (one instruction for the pair), lo = rn_bf16(x - hi), where x - hi is exact;
+// lo = 0 where x - hi is not finite (x NaN or infinite, or hi rounded up to
+// infinity), so that no lo product turns a finite or infinite result into NaN.
+__device__ __forceinline__ void split_pair(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+    const f32x2 x = {x0, x1};
+    hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf16x2));
+    float r0 = x0 - __builtin_bit_cast(float, hi << 16);
+    float r1 = x1 - __builtin_bit_cast(float, hi & 0xffff0000u);
+    r0 = __builtin_isfinite(r0) ? r0 : 0.f;
+    r1 = __builtin_isfinite(r1) ? r1 : 0.f;
+    const f32x2 r = {r0, r1};
+    lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2));
 }
 
 // Pack stage of one operand for the split mode: each thread gathers pairs of
@@ -882,12 +886,11 @@ struct PackPair {
 #pragma unroll
         for (int i = 0; i < EP; ++i) {
             const int q = t + NTHR * i;
-            uint32_t h0, l0, h1, l1;
-            split_bf16(r0[i], h0, l0);
-            split_bf16(r1[i], h1, l1);
+            uint32_t h, l;
+            split_pair(r0[i], r1[i], h, l);
             const int w = (ridx(q) * KTP + 2 * pidx(q)) >> 1;
-            hi[w] = h0 | (h1 << 16);
-            lo[w] = l0 | (l1 << 16);
+            hi[w] = h;
+            lo[w] = l;
         }
     }
 };
