@@ -9,6 +9,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -33,10 +34,13 @@ struct tc_batch {
     struct Segment {
         int tile, first, count, grid;
         int64_t items;
+        size_t off_pos, ent_pos;  // the launch's work lists inside `assign` (int32 units)
     };
     std::vector<Segment> segs;  // launches, in issue order
     void* table = nullptr;      // device BatchItemDev[count]
     void* vectors = nullptr;    // device arena holding every problem's vectors
+    void* assign = nullptr;     // device int32: per launch, workgroup offsets then (problem, tile) entries
+    size_t assign_cap = 0;      // bytes allocated for `assign`
 };
 
 namespace tc {
@@ -614,6 +618,67 @@ static int batch_layout(tc_batch* b) {
         }
         b->grid = std::max(b->grid, sg.grid);
     }
+    // Work lists: within each launch, the (problem, tile) work items in
+    // decreasing cost (the table is in decreasing k inside a class; every tile
+    // of a problem costs the same), each given to the workgroup with the least
+    // work so far, ties to the lower index (longest processing time first).
+    // The lists are fixed here, so a launch needs no counter and no reset
+    // between graph replays, and the assignment is deterministic.  Cost of a
+    // tile: its k plus three stages for the prologue and the C update.
+    std::vector<int32_t> host;
+    for (auto& sg : b->segs) {
+        const TileCfg& t = tab[sg.tile];
+        const int G = sg.grid;
+        std::vector<std::vector<int32_t>> lists((size_t)std::max(G, 1));
+        typedef std::pair<double, int> Load;  // (work so far, workgroup)
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+        for (int g = 0; g < G; ++g) heap.push({0.0, g});
+        for (int e = 0; e < sg.count; ++e) {
+            const BatchItemDev& it = table[(size_t)(sg.first + e)];
+            const int64_t tiles = it.tiles_m * it.tiles_n;
+            if (tiles > 0x7fffffffLL) {
+                set_error("a batch problem has more than 2^31 tiles");
+                return TC_ERR_ARG;
+            }
+            const double cost = (double)std::max<int64_t>(it.k, 1) + 3.0 * t.KT;
+            for (int64_t w = 0; w < tiles; ++w) {
+                Load l = heap.top();
+                heap.pop();
+                lists[(size_t)l.second].push_back(e);
+                lists[(size_t)l.second].push_back((int32_t)w);
+                heap.push({l.first + cost, l.second});
+            }
+        }
+        sg.off_pos = host.size();
+        size_t run = 0;
+        for (int g = 0; g <= G; ++g) {
+            if ((int64_t)run > 0x7fffffffLL) {
+                set_error("too many work items in one batched launch");
+                return TC_ERR_ARG;
+            }
+            host.push_back((int32_t)run);
+            if (g < G) run += lists[(size_t)g].size() / 2;
+        }
+        sg.ent_pos = host.size();
+        for (int g = 0; g < G; ++g) host.insert(host.end(), lists[(size_t)g].begin(), lists[(size_t)g].end());
+    }
+    const size_t bytes = std::max<size_t>(host.size(), 1) * sizeof(int32_t);
+    if (bytes > b->assign_cap) {
+        if (b->assign) hipFree(b->assign);
+        b->assign = nullptr;
+        b->assign_cap = 0;
+        hipError_t e = hipMalloc(&b->assign, bytes);
+        if (e != hipSuccess) {
+            b->assign = nullptr;
+            set_error("hipMalloc of the batch work lists failed");
+            return TC_ERR_NOMEM;
+        }
+        b->assign_cap = bytes;
+    }
+    if (!host.empty()) {
+        hipError_t e = hipMemcpy(b->assign, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hipfail(e, "hipMemcpy of the batch work lists");
+    }
     return TC_OK;
 }
 
@@ -846,9 +911,10 @@ int tc_batch_execute(const tc_batch* batch, void* stream) {
     }
     for (const auto& sg : batch->segs) {
         if (sg.items == 0) continue;
+        const int32_t* lists = (const int32_t*)batch->assign;
         int st = launch_batch(batch->dtype, batch->mode, sg.tile, batch->off64,
-                              (const BatchItemDev*)batch->table + sg.first, sg.count, sg.items, sg.grid,
-                              (hipStream_t)stream);
+                              (const BatchItemDev*)batch->table + sg.first, lists + sg.off_pos, lists + sg.ent_pos,
+                              sg.items, sg.grid, (hipStream_t)stream);
         if (st) return st;
     }
     return TC_OK;
@@ -923,6 +989,7 @@ int tc_batch_destroy(tc_batch* batch) {
     if (!batch) return TC_OK;
     if (batch->table) hipFree(batch->table);
     if (batch->vectors) hipFree(batch->vectors);
+    if (batch->assign) hipFree(batch->assign);
     delete batch;
     return TC_OK;
 }

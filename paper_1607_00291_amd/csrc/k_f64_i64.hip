@@ -9,9 +9,9 @@ int launch_typed_f64_i64(const Plan& p, const DeviceVectors& dv, double alpha, c
     return launch_typed<double, int64_t>(p, dv, alpha, A, B, beta, C, s);
 }
 
-int batch_dispatch_f64_i64(int dtype, int tile, bool launch, const BatchItemDev* items, int count, int64_t total, int grid,
-                         hipStream_t s) {
-    return batch_dispatch<double, int64_t>(dtype, tile, launch, items, count, total, grid, s);
+int batch_dispatch_f64_i64(int dtype, int tile, bool launch, const BatchItemDev* items, const int32_t* off,
+                         const int32_t* ent, int64_t total, int grid, hipStream_t s) {
+    return batch_dispatch<double, int64_t>(dtype, tile, launch, items, off, ent, total, grid, s);
 }
 
 }  // namespace tc

@@ -11,20 +11,20 @@ namespace tc {
 
 int launch_typed_f64_i32(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
                        void* C, hipStream_t s);
-int batch_dispatch_f64_i32(int dtype, int tile, bool launch, const BatchItemDev* items, int count, int64_t total, int grid,
-                         hipStream_t s);
+int batch_dispatch_f64_i32(int dtype, int tile, bool launch, const BatchItemDev* items, const int32_t* off,
+                         const int32_t* ent, int64_t total, int grid, hipStream_t s);
 int launch_typed_f64_i64(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
                        void* C, hipStream_t s);
-int batch_dispatch_f64_i64(int dtype, int tile, bool launch, const BatchItemDev* items, int count, int64_t total, int grid,
-                         hipStream_t s);
+int batch_dispatch_f64_i64(int dtype, int tile, bool launch, const BatchItemDev* items, const int32_t* off,
+                         const int32_t* ent, int64_t total, int grid, hipStream_t s);
 int launch_typed_f32_i32(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
                        void* C, hipStream_t s);
-int batch_dispatch_f32_i32(int dtype, int tile, bool launch, const BatchItemDev* items, int count, int64_t total, int grid,
-                         hipStream_t s);
+int batch_dispatch_f32_i32(int dtype, int tile, bool launch, const BatchItemDev* items, const int32_t* off,
+                         const int32_t* ent, int64_t total, int grid, hipStream_t s);
 int launch_typed_f32_i64(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
                        void* C, hipStream_t s);
-int batch_dispatch_f32_i64(int dtype, int tile, bool launch, const BatchItemDev* items, int count, int64_t total, int grid,
-                         hipStream_t s);
+int batch_dispatch_f32_i64(int dtype, int tile, bool launch, const BatchItemDev* items, const int32_t* off,
+                         const int32_t* ent, int64_t total, int grid, hipStream_t s);
 
 int launch_plan(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
                 void* C, hipStream_t s) {
@@ -39,27 +39,27 @@ int launch_plan(const Plan& p, const DeviceVectors& dv, double alpha, const void
                    : launch_typed_f32_i32(p, dv, alpha, A, B, beta, C, s);
 }
 
-int launch_batch(int dtype, int mode, int tile, bool off64, const BatchItemDev* items, int count, int64_t total,
-                 int grid, hipStream_t s) {
+int launch_batch(int dtype, int mode, int tile, bool off64, const BatchItemDev* items, const int32_t* off,
+                 const int32_t* ent, int64_t total, int grid, hipStream_t s) {
     if (mode != TC_NATIVE) {
         set_error("batched launches support the native modes");
         return TC_ERR_DTYPE;
     }
     if (total <= 0) return TC_OK;
     if (dtype == TC_F64)
-        return off64 ? batch_dispatch_f64_i64(dtype, tile, true, items, count, total, grid, s)
-                     : batch_dispatch_f64_i32(dtype, tile, true, items, count, total, grid, s);
-    return off64 ? batch_dispatch_f32_i64(dtype, tile, true, items, count, total, grid, s)
-                 : batch_dispatch_f32_i32(dtype, tile, true, items, count, total, grid, s);
+        return off64 ? batch_dispatch_f64_i64(dtype, tile, true, items, off, ent, total, grid, s)
+                     : batch_dispatch_f64_i32(dtype, tile, true, items, off, ent, total, grid, s);
+    return off64 ? batch_dispatch_f32_i64(dtype, tile, true, items, off, ent, total, grid, s)
+                 : batch_dispatch_f32_i32(dtype, tile, true, items, off, ent, total, grid, s);
 }
 
 int batch_grid(int dtype, int mode, int tile, bool off64, int64_t total) {
     if (mode != TC_NATIVE || total <= 0) return 0;
     if (dtype == TC_F64)
-        return off64 ? batch_dispatch_f64_i64(dtype, tile, false, nullptr, 0, total, 0, nullptr)
-                     : batch_dispatch_f64_i32(dtype, tile, false, nullptr, 0, total, 0, nullptr);
-    return off64 ? batch_dispatch_f32_i64(dtype, tile, false, nullptr, 0, total, 0, nullptr)
-                 : batch_dispatch_f32_i32(dtype, tile, false, nullptr, 0, total, 0, nullptr);
+        return off64 ? batch_dispatch_f64_i64(dtype, tile, false, nullptr, nullptr, nullptr, total, 0, nullptr)
+                     : batch_dispatch_f64_i32(dtype, tile, false, nullptr, nullptr, nullptr, total, 0, nullptr);
+    return off64 ? batch_dispatch_f32_i64(dtype, tile, false, nullptr, nullptr, nullptr, total, 0, nullptr)
+                 : batch_dispatch_f32_i32(dtype, tile, false, nullptr, nullptr, nullptr, total, 0, nullptr);
 }
 
 }  // namespace tc

@@ -814,7 +814,7 @@ __device__ __forceinline__ void split_pair(float x0, float x1, uint32_t& hi, uin
 // consecutive k of one row (the pair is one 32-bit LDS word per plane).
 // Planes are row-major [R][KTP] bf16 (k contiguous), the order in which the
 // bf16 matrix-core operands read 8 consecutive k per lane.
-template <typename OffT, int R, int KT, int NTHR, bool LR>
+template <typename OffT, int R, int KT, int NTHR, bool LR, int SLOTS = 1>
 struct PackPair {
     static constexpr int KP = KT / 2;
     static constexpr int EP = R * KP / NTHR;  // pairs per thread
@@ -824,7 +824,7 @@ struct PackPair {
     static __device__ __forceinline__ int ridx(int q) { return LR ? q % R : q / KP; }
     static __device__ __forceinline__ int pidx(int q) { return LR ? q / R : q % KP; }
     OffT o[EP];
-    float r0[EP], r1[EP];
+    float r0[SLOTS][EP], r1[SLOTS][EP];  // stages in flight
     __device__ __forceinline__ void init(const OffT* rowvec, OffT r0_, OffT rmax, int t) {
 #pragma unroll
         for (int i = 0; i < EP; ++i) {
@@ -835,7 +835,7 @@ struct PackPair {
     }
     // REG = 1: every k block of this operand has a block stride (no per-k
     // offset reads compiled in); REG = -1: decided per block.
-    template <int REG = -1>
+    template <int REG = -1, int SL = 0>
     __device__ __forceinline__ void load(const float* base, int64_t span, const OffT* kvec, const OffT* kbs, OffT kb,
                                          OffT K, int t) {
         const OffT k0 = kb * KT;
@@ -865,8 +865,8 @@ struct PackPair {
             for (int i = 0; i < EP; ++i) {
                 const OffT kg = k0 + 2 * pidx(t + NTHR * i);
                 const bool ok0 = o[i] >= 0 && kg < K, ok1 = o[i] >= 0 && kg + 1 < K;
-                r0[i] = buf_load<float>(rs, ok0 ? (uint32_t)(o[i] + ko0[i]) * 4u : kOutOfRange, soff);
-                r1[i] = buf_load<float>(rs, ok1 ? (uint32_t)(o[i] + ko1[i]) * 4u : kOutOfRange, soff);
+                r0[SL][i] = buf_load<float>(rs, ok0 ? (uint32_t)(o[i] + ko0[i]) * 4u : kOutOfRange, soff);
+                r1[SL][i] = buf_load<float>(rs, ok1 ? (uint32_t)(o[i] + ko1[i]) * 4u : kOutOfRange, soff);
             }
         } else {
 #pragma unroll
@@ -875,19 +875,20 @@ struct PackPair {
                 const bool ok0 = o[i] >= 0 && kg < K, ok1 = o[i] >= 0 && kg + 1 < K;
                 const float x0 = base[ok0 ? kbase + o[i] + ko0[i] : OffT(0)];
                 const float x1 = base[ok1 ? kbase + o[i] + ko1[i] : OffT(0)];
-                r0[i] = ok0 ? x0 : 0.f;
-                r1[i] = ok1 ? x1 : 0.f;
+                r0[SL][i] = ok0 ? x0 : 0.f;
+                r1[SL][i] = ok1 ? x1 : 0.f;
             }
         }
     }
     // hi plane at `hi`, lo plane at hi + PLANE (both as 32-bit words)
+    template <int SL = 0>
     __device__ __forceinline__ void store(uint32_t* hi, int t) const {
         uint32_t* lo = hi + PLANE / 2;
 #pragma unroll
         for (int i = 0; i < EP; ++i) {
             const int q = t + NTHR * i;
             uint32_t h, l;
-            split_pair(r0[i], r1[i], h, l);
+            split_pair(r0[SL][i], r1[SL][i], h, l);
             const int w = (ridx(q) * KTP + 2 * pidx(q)) >> 1;
             hi[w] = h;
             lo[w] = l;
@@ -902,8 +903,11 @@ struct TileSplit {
     static constexpr int WTM = MT / WM, WTN = NT / WN;
     static constexpr int FM = WTM / 16, FN = WTN / 16;
     static_assert(KT % 32 == 0, "KT must be a multiple of the bf16 matrix-core depth");
-    typedef PackPair<OffT, MT, KT, NTHR, XM> PX;
-    typedef PackPair<OffT, NT, KT, NTHR, YN> PY;
+    // gathered stages in flight in registers (measured: one for the 3 x 3
+    // wave 144 tile, whose 576 threads leave 168 registers per thread)
+    static constexpr int SLOTS = MT == 144 ? 1 : 2;
+    typedef PackPair<OffT, MT, KT, NTHR, XM, SLOTS> PX;
+    typedef PackPair<OffT, NT, KT, NTHR, YN, SLOTS> PY;
     // one stage: X hi, X lo, Y hi, Y lo planes (in bf16 elements)
     static constexpr int STAGE = 2 * PX::PLANE + 2 * PY::PLANE;
     static constexpr int SMEM = 2 * STAGE / 2;  // in floats (two stages of bf16 = STAGE floats)
@@ -932,26 +936,19 @@ struct TileSplit {
         auto xs = [&](int buf) { return smem + buf * STAGE; };
         auto ys = [&](int buf) { return smem + buf * STAGE + 2 * PX::PLANE; };
         const OffT nkb = (a.k + KT - 1) / KT;
-        // the gathers of stage kb + 1 and their LDS store run with no branch
-        // around them (past the last stage they re-read the last block and
-        // fill the LDS buffer no stage reads any more), and a regular-k
-        // operand pair gets its own compiled path; the 128 x 128 tile keeps
-        // the guarded form, which measured faster for it
-        constexpr bool BF = !(MT == 128 && NT == 128);
-        auto pipeline = [&](auto reg) {
+        // Stage kb + SLOTS is gathered into register slot kb % SLOTS while
+        // the matrix cores consume LDS stage kb, and stage kb + 1 (gathered
+        // SLOTS - 1 stages earlier) is split into the other LDS buffer.  The
+        // gathers and stores run with no branch around them: past the last
+        // stage they re-read the last block into a buffer no stage reads.
+        auto body = [&](OffT kb, auto slot, auto reg) {
+            constexpr int SL = decltype(slot)::value;
             constexpr int RG = decltype(reg)::value;
-            px.template load<RG>(a.X, a.spanX, a.cX, a.kbsX, 0, a.k, tid);
-            py.template load<RG>(a.Y, a.spanY, a.rY, a.kbsY, 0, a.k, tid);
-            px.store((uint32_t*)xs(0), tid);
-            py.store((uint32_t*)ys(0), tid);
-            __syncthreads();
-            for (OffT kb = 0; kb < nkb; ++kb) {
-                const int buf = (int)(kb & 1);
-                const OffT kn = kb + 1 < nkb ? kb + 1 : kb;
-                if (BF || kb + 1 < nkb) {
-                    px.template load<RG>(a.X, a.spanX, a.cX, a.kbsX, kn, a.k, tid);
-                    py.template load<RG>(a.Y, a.spanY, a.rY, a.kbsY, kn, a.k, tid);
-                }
+            const int buf = (int)(kb & 1);
+            const OffT lk = kb + SLOTS < nkb ? kb + SLOTS : nkb - 1;
+            px.template load<RG, SL>(a.X, a.spanX, a.cX, a.kbsX, lk, a.k, tid);
+            py.template load<RG, SL>(a.Y, a.spanY, a.rY, a.kbsY, lk, a.k, tid);
+            if (kb < nkb) {
                 const __bf16* xh = xs(buf) + (wm * WTM + (lane & 15)) * PX::KTP + 8 * (lane >> 4);
                 const __bf16* yh = ys(buf) + (wn * WTN + (lane & 15)) * PY::KTP + 8 * (lane >> 4);
 #pragma unroll
@@ -976,29 +973,295 @@ struct TileSplit {
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
                         }
                 }
-                if (BF || kb + 1 < nkb) {
-                    px.store((uint32_t*)xs(buf ^ 1), tid);
-                    py.store((uint32_t*)ys(buf ^ 1), tid);
-                }
-                __syncthreads();
             }
+            px.template store<(SL + 1) % SLOTS>((uint32_t*)xs(buf ^ 1), tid);
+            py.template store<(SL + 1) % SLOTS>((uint32_t*)ys(buf ^ 1), tid);
+            __syncthreads();
+        };
+        auto pipeline = [&](auto reg) {
+            constexpr int RG = decltype(reg)::value;
+            static_for<SLOTS>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                const OffT lk = nkb > i ? (OffT)i : nkb - 1;
+                px.template load<RG, i>(a.X, a.spanX, a.cX, a.kbsX, lk, a.k, tid);
+                py.template load<RG, i>(a.Y, a.spanY, a.rY, a.kbsY, lk, a.k, tid);
+            });
+            px.template store<0>((uint32_t*)xs(0), tid);
+            py.template store<0>((uint32_t*)ys(0), tid);
+            __syncthreads();
+            for (OffT kb = 0; kb < nkb; kb += SLOTS)
+                static_for<SLOTS>([&](auto ic) { body(kb + decltype(ic)::value, ic, reg); });
         };
         if (nkb > 0) {
-            if (BF && a.kregX && a.kregY) pipeline(std::integral_constant<int, 1>());
+            if (a.kregX && a.kregY) pipeline(std::integral_constant<int, 1>());
             else pipeline(std::integral_constant<int, -1>());
         }
         store_rect<float, OffT, M, FM, FN, false>(a, &acc[0][0], (OffT)(m0 + wm * WTM), (OffT)(n0 + wn * WTN), lane);
     }
 };
 
+// Pack stage of one operand for the warp-specialised split tile: a thread
+// gathers quads of four consecutive k of one row (four loads in flight per
+// quad), splits them into two hi and two lo words and writes each pair of
+// words with one 64-bit LDS store.  Planes are [R][KTP] bf16 (k contiguous);
+// a quad's element order follows the operand's lanes, as in PackRole.
+template <typename OffT, int R, int KT, int NTHR, int KTP, int SLOTS>
+struct PackQuad {
+    static constexpr int KQ = KT / 4;         // quads per row
+    static constexpr int EQ = R * KQ / NTHR;  // quads per thread
+    static constexpr int PLANE = R * KTP;     // bf16 elements of one plane
+    static_assert((R * KQ) % NTHR == 0, "stage must split evenly over threads");
+    static_assert(KTP % 4 == 0, "64-bit LDS stores need an even word pitch");
+    OffT o[EQ];  // row offsets, -1 past the edge
+    float v[SLOTS][EQ][4];
+    bool lr;  // lanes along the free index (else along k)
+    __device__ __forceinline__ int ridx(int q) const { return lr ? q % R : q / KQ; }
+    __device__ __forceinline__ int qidx(int q) const { return lr ? q / R : q % KQ; }
+    __device__ __forceinline__ void init(const OffT* rowvec, OffT r0, OffT rmax, int t, bool lanes_row) {
+        lr = lanes_row;
+#pragma unroll
+        for (int i = 0; i < EQ; ++i) {
+            const OffT rr = r0 + ridx(t + NTHR * i);
+            const OffT x = rowvec[rr < rmax ? rr : rmax - 1];
+            o[i] = rr < rmax ? x : OffT(-1);
+        }
+    }
+    // Gather of k block kb.  REG = 1: every k block has a block stride sk,
+    // so k offsets are kk * sk from the block's first k offset (one scalar);
+    // REG = 0: per-k offsets from the scatter vector.
+    template <int SL, int REG>
+    __device__ __forceinline__ void load_with(OffT sk, OffT kfirst, const float* base, int64_t span, const OffT* kvec,
+                                              OffT kb, OffT K, int t) {
+        const OffT k0 = kb * KT;
+        if constexpr (sizeof(OffT) == 4) {
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(base, span);
+            const uint32_t soff = REG >= 1 ? (uint32_t)uniform((int32_t)((uint32_t)kfirst * 4u)) : 0u;
+#pragma unroll
+            for (int i = 0; i < EQ; ++i) {
+                const OffT kq = 4 * (OffT)qidx(t + NTHR * i);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const OffT kg = k0 + kq + j;
+                    const bool ok = o[i] >= 0 && kg < K;
+                    const OffT ko = REG >= 1 ? (kq + j) * sk : kvec[kg < K ? kg : K - 1];
+                    v[SL][i][j] = buf_load<float>(rs, ok ? (uint32_t)(o[i] + ko) * 4u : kOutOfRange, soff);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < EQ; ++i) {
+                const OffT kq = 4 * (OffT)qidx(t + NTHR * i);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const OffT kg = k0 + kq + j;
+                    const bool ok = o[i] >= 0 && kg < K;
+                    const OffT ko = REG >= 1 ? kfirst + (kq + j) * sk : kvec[kg < K ? kg : K - 1];
+                    const float x = base[ok ? o[i] + ko : OffT(0)];
+                    v[SL][i][j] = ok ? x : 0.f;
+                }
+            }
+        }
+    }
+    // split and store: hi plane at `hi`, lo plane at hi + PLANE (as words)
+    template <int SL>
+    __device__ __forceinline__ void store(uint32_t* hi, int t) const {
+        uint32_t* lo = hi + PLANE / 2;
+#pragma unroll
+        for (int i = 0; i < EQ; ++i) {
+            const int q = t + NTHR * i;
+            uint32_t h0, l0, h1, l1;
+            split_pair(v[SL][i][0], v[SL][i][1], h0, l0);
+            split_pair(v[SL][i][2], v[SL][i][3], h1, l1);
+            const int w = (ridx(q) * KTP + 4 * qidx(q)) >> 1;
+            typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+            *(u32x2*)(hi + w) = u32x2{h0, h1};
+            *(u32x2*)(lo + w) = u32x2{l0, l1};
+        }
+    }
+};
+
+// Split mode on the pinwheel with specialised waves (MT = NT = 144, eight
+// waves): waves 0-3 (one per SIMD) each own one whole 4x5 / 5x4 rectangle of
+// the 9 x 9 fragment grid (a 5x4 one run as the 4x5 rectangle of C^T) and only
+// read bf16 fragments from LDS and issue the three products per fragment;
+// waves 4-7 gather, split and store both operands (4 and 5 the X sliver, 6
+// and 7 the Y sliver), two stages in flight, and waves 4, 5 and 6 each run
+// one of the three products of the centre fragment.  This keeps the split's
+// vector work off the compute waves and gives every SIMD the same matrix work
+// (the 3 x 3 wave grid puts three waves on one SIMD).
+template <typename OffT, int KT, bool XM, bool YN>
+struct TileSplitWS {
+    static constexpr int MT = 144, NT = 144, NTHR = 512;
+    static_assert(KT % 32 == 0, "KT must be a multiple of the bf16 matrix-core depth");
+    static constexpr int KTP = KT + 8;  // plane pitch in bf16 (16-byte multiple)
+    static constexpr int SLOTS = 2;     // gathered stages in flight per producer thread
+    typedef PackQuad<OffT, 144, KT, 128, KTP, SLOTS> PQ;
+    static constexpr int PLANE = PQ::PLANE;
+    static constexpr int STAGE = 4 * PLANE;  // X hi, X lo, Y hi, Y lo (bf16 elements)
+    static constexpr int SMEM = STAGE > 3 * 256 ? STAGE : 3 * 256;  // two stages, in floats
+
+    static __device__ __forceinline__ bf16x8 ld8(const __bf16* p) { return *(const bf16x8*)p; }
+
+    static __device__ __forceinline__ void run(const KArgs<float, OffT>& a, int64_t tile, float* smemf) {
+        typedef Mfma<float> M;
+        __bf16* smem = (__bf16*)smemf;
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int64_t tm = tile % a.tiles_m, tn = tile / a.tiles_m;
+        const OffT m0 = (OffT)(tm * MT), n0 = (OffT)(tn * NT);
+        const OffT nkb = (a.k + KT - 1) / KT;
+        // operand planes of stage buffer b: X at [0, 2 PLANE), Y at [2 PLANE, 4 PLANE)
+        auto xplane = [&](int b) { return smem + b * STAGE; };
+        auto yplane = [&](int b) { return smem + b * STAGE + 2 * PLANE; };
+        const int rl = lane & 15, kl = 8 * (lane >> 4);
+        if (wave >= 4) {
+            // ---- producer waves ----
+            const bool gx = wave < 6;
+            const int tt = tid & 127;
+            const float* gbase = gx ? a.X : a.Y;
+            const int64_t gspan = gx ? a.spanX : a.spanY;
+            const OffT* gk = gx ? a.cX : a.rY;
+            const OffT* gbs = gx ? a.kbsX : a.kbsY;
+            PQ pk;
+            if (gx) pk.init(a.rX, m0, a.m, tt, XM);
+            else pk.init(a.cY, n0, a.n, tt, YN);
+            f32x4 accc = {0.f, 0.f, 0.f, 0.f};
+            OffT pre_sk = 0, pre_k = 0;
+            auto fetch = [&](OffT kb) {
+                pre_sk = uniform(gbs[kb]);
+                pre_k = uniform(gk[kb * KT]);
+            };
+            auto body = [&](OffT kb, auto slot, auto reg) {
+                constexpr int SL = decltype(slot)::value;
+                constexpr int RG = decltype(reg)::value;
+                const int buf = (int)(kb & 1);
+                const OffT lk = kb + SLOTS < nkb ? kb + SLOTS : nkb - 1;
+                pk.template load_with<SL, RG>(pre_sk, pre_k, gbase, gspan, gk, lk, a.k, tt);
+                fetch(kb + SLOTS + 1 < nkb ? kb + SLOTS + 1 : nkb - 1);
+                if (kb < nkb && wave < 7) {
+                    // one of the centre fragment's three products: wave 4
+                    // lo*hi, wave 5 hi*lo, wave 6 hi*hi
+                    const __bf16* xc = xplane(buf) + (64 + rl) * KTP + kl;
+                    const __bf16* yc = yplane(buf) + (64 + rl) * KTP + kl;
+#pragma unroll
+                    for (int s = 0; s < KT / 32; ++s) {
+                        const bf16x8 ca = ld8(xc + (wave == 4 ? PLANE : 0) + 32 * s);
+                        const bf16x8 cb = ld8(yc + (wave == 5 ? PLANE : 0) + 32 * s);
+                        accc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, cb, accc, 0, 0, 0);
+                    }
+                }
+                pk.template store<(SL + 1) % SLOTS>((uint32_t*)(gx ? xplane(buf ^ 1) : yplane(buf ^ 1)), tt);
+                __syncthreads();
+            };
+            auto pipeline = [&](auto reg) {
+                constexpr int RG = decltype(reg)::value;
+                static_for<SLOTS>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    fetch(nkb > i ? i : nkb - 1);
+                    pk.template load_with<i, RG>(pre_sk, pre_k, gbase, gspan, gk, nkb > i ? i : nkb - 1, a.k, tt);
+                });
+                pk.template store<0>((uint32_t*)(gx ? xplane(0) : yplane(0)), tt);
+                fetch(nkb > SLOTS ? SLOTS : nkb - 1);
+                __syncthreads();
+                for (OffT kb = 0; kb < nkb; kb += SLOTS)
+                    static_for<SLOTS>([&](auto ic) { body(kb + decltype(ic)::value, ic, reg); });
+            };
+            if (nkb > 0) {
+                if (gx ? a.kregX : a.kregY) pipeline(std::integral_constant<int, 1>());
+                else pipeline(std::integral_constant<int, 0>());
+            }
+            // centre fragment: the three products added in a fixed order
+            if (wave < 7) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) smemf[(wave - 4) * 256 + r * 64 + lane] = accc[r];
+            }
+            __syncthreads();
+            if (wave == 4) {
+                f32x4 v;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    v[r] = (smemf[r * 64 + lane] + smemf[256 + r * 64 + lane]) + smemf[512 + r * 64 + lane];
+                store_frag<float, OffT>(a, (OffT)(m0 + 64), (OffT)(n0 + 64), v, lane);
+            }
+            return;
+        }
+        // ---- compute waves ----
+        const int q = wave;
+        const bool wide = (q & 1) == 0;
+        const int fr0 = q == 0 ? 0 : q == 1 ? 0 : q == 2 ? 5 : 4;
+        const int fc0 = q == 0 ? 0 : q == 1 ? 5 : q == 2 ? 4 : 0;
+        const int p0 = wide ? fr0 : fc0, q0 = wide ? fc0 : fr0;
+        f32x4 acc[20];
+#pragma unroll
+        for (int f = 0; f < 20; ++f) acc[f] = f32x4{0.f, 0.f, 0.f, 0.f};
+        auto stage = [&](OffT kb) {
+            const int buf = (int)(kb & 1);
+            if (kb < nkb) {
+                const __bf16* pp = (wide ? xplane(buf) : yplane(buf)) + (16 * p0 + rl) * KTP + kl;
+                const __bf16* qp = (wide ? yplane(buf) : xplane(buf)) + (16 * q0 + rl) * KTP + kl;
+#pragma unroll
+                for (int s = 0; s < KT / 32; ++s) {
+                    bf16x8 bh[5], bl[5];
+#pragma unroll
+                    for (int j = 0; j < 5; ++j) {
+                        bh[j] = ld8(qp + 16 * j * KTP + 32 * s);
+                        bl[j] = ld8(qp + PLANE + 16 * j * KTP + 32 * s);
+                    }
+                    // one A fragment row at a time, the next read over the
+                    // current row's products
+                    bf16x8 ah[2], al[2];
+                    ah[0] = ld8(pp + 32 * s);
+                    al[0] = ld8(pp + PLANE + 32 * s);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (i + 1 < 4) {
+                            ah[(i + 1) & 1] = ld8(pp + 16 * (i + 1) * KTP + 32 * s);
+                            al[(i + 1) & 1] = ld8(pp + PLANE + 16 * (i + 1) * KTP + 32 * s);
+                        }
+#pragma unroll
+                        for (int j = 0; j < 5; ++j) {
+                            f32x4& c = acc[i * 5 + j];
+                            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i & 1], bh[j], c, 0, 0, 0);
+                            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i & 1], bl[j], c, 0, 0, 0);
+                            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i & 1], bh[j], c, 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        };
+        if (nkb > 0) {
+            __syncthreads();  // the producers' first stage
+            for (OffT kb = 0; kb < nkb; kb += SLOTS)
+#pragma unroll
+                for (int i = 0; i < SLOTS; ++i) stage(kb + i);
+        }
+        __syncthreads();  // the producers' centre reduction
+        if (wide) rect_store<float, OffT, M, 4, 5>(a, acc, m0, n0, fr0, fc0, lane);
+        else rect_store_t<float, OffT, M, 4, 5>(a, acc, m0, n0, fc0, fr0, lane);
+    }
+};
+
+template <typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT, bool XM, bool YN>
+struct SplitTileOf {
+    typedef TileSplit<OffT, MT, NT, KT, WM, WN, XM, YN> type;
+    static constexpr int threads = WM * WN * 64;
+};
 template <typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
-__global__ __launch_bounds__(WM* WN * 64) void split_kernel(KArgs<float, OffT> a) {
-    typedef TileSplit<OffT, MT, NT, KT, WM, WN, XM, YN> Tile;
+struct SplitTileOf<OffT, MT, NT, KT, WM, WN, 2, XM, YN> {
+    typedef TileSplitWS<OffT, KT, XM, YN> type;
+    static constexpr int threads = 512;
+};
+
+template <typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT, bool XM, bool YN>
+__global__ __launch_bounds__((SplitTileOf<OffT, MT, NT, KT, WM, WN, LAYOUT, XM, YN>::threads)) void split_kernel(
+    KArgs<float, OffT> a) {
+    typedef typename SplitTileOf<OffT, MT, NT, KT, WM, WN, LAYOUT, XM, YN>::type Tile;
     __shared__ float smem[Tile::SMEM];
     Tile::run(a, xcd_tile(blockIdx.x, a.tiles_m, a.tiles_n), smem);
 }
 
-template <typename OffT, int MT, int NT, int KT, int WM, int WN>
+template <typename OffT, int MT, int NT, int KT, int WM, int WN, int L>
 static int launch_split_tile(const KArgs<float, OffT>& a, bool xm, bool yn, hipStream_t s) {
     const int64_t tiles = a.tiles_m * a.tiles_n;
     if (tiles <= 0) return TC_OK;
@@ -1006,11 +1269,11 @@ static int launch_split_tile(const KArgs<float, OffT>& a, bool xm, bool yn, hipS
         set_error("too many tiles for one launch");
         return TC_ERR_ARG;
     }
-    dim3 grid((unsigned)tiles), block(WM * WN * 64);
-    if (xm && yn) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, true, true>), grid, block, 0, s, a);
-    else if (xm) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, true, false>), grid, block, 0, s, a);
-    else if (yn) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, false, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, false, false>), grid, block, 0, s, a);
+    dim3 grid((unsigned)tiles), block(SplitTileOf<OffT, MT, NT, KT, WM, WN, L, true, true>::threads);
+    if (xm && yn) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, true, true>), grid, block, 0, s, a);
+    else if (xm) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, true, false>), grid, block, 0, s, a);
+    else if (yn) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, false, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, false, false>), grid, block, 0, s, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? TC_OK : hip_fail(e, "kernel launch");
 }
@@ -1293,7 +1556,7 @@ static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, co
         if (p.mode == TC_SPLIT_BF16X3) {
 #define TC_SCASE(id, MT, NT, KT, WM, WN, L) \
     case id:                                \
-        return launch_split_tile<OffT, MT, NT, KT, WM, WN>(a, xm, yn, s);
+        return launch_split_tile<OffT, MT, NT, KT, WM, WN, L>(a, xm, yn, s);
             switch (p.tile) { TC_TILES_BF16X3(TC_SCASE) }
 #undef TC_SCASE
             set_error("unknown tile configuration");
@@ -1313,14 +1576,13 @@ static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, co
     return TC_ERR_ARG;
 }
 
-// Persistent batched kernel: workgroup g processes work items g, g + G, ...
-// of a flattened (problem, tile) list; problems are ordered by decreasing
-// cost per tile, so the static stride assignment stays balanced.  Every
-// problem may have its own lane directions, so the four pack variants are
-// dispatched per item.
+// Persistent batched kernel: workgroup g runs its own list of (problem,
+// tile) work items, fixed on the host by a longest-processing-time-first
+// assignment.  Every problem may have its own lane directions, so the four
+// pack variants are dispatched per item.
 template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int L>
 __global__ __launch_bounds__((TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, true>::threads)) void batch_kernel(
-    const BatchItemDev* __restrict__ items, int count, int64_t total) {
+    const BatchItemDev* __restrict__ items, const int32_t* __restrict__ off, const int32_t* __restrict__ ent) {
     typedef typename TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, true>::type TTT;
     typedef typename TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, false>::type TTF;
     typedef typename TileOf<T, OffT, MT, NT, KT, WM, WN, L, false, true>::type TFT;
@@ -1328,14 +1590,10 @@ __global__ __launch_bounds__((TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, true>
     constexpr int S1 = TTT::SMEM > TTF::SMEM ? TTT::SMEM : TTF::SMEM;
     constexpr int S2 = TFT::SMEM > TFF::SMEM ? TFT::SMEM : TFF::SMEM;
     __shared__ T smem[S1 > S2 ? S1 : S2];
-    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-        int lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (items[mid].first_item <= w) lo = mid;
-            else hi = mid - 1;
-        }
-        const BatchItemDev& it = items[lo];
+    const int32_t j0 = uniform(off[blockIdx.x]), j1 = uniform(off[blockIdx.x + 1]);
+    for (int32_t j = j0; j < j1; ++j) {
+        const BatchItemDev& it = items[uniform(ent[2 * j])];
+        const int64_t tile = uniform(ent[2 * j + 1]);
         KArgs<T, OffT> a;
         a.X = (const T*)it.X;
         a.Y = (const T*)it.Y;
@@ -1361,7 +1619,6 @@ __global__ __launch_bounds__((TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, true>
         a.kregY = it.kregY;
         a.ksX = 0;  // per-tile byte offsets are not formed in batched launches
         a.ksY = 0;
-        const int64_t tile = w - it.first_item;
         if (it.x_lanes_m) {
             if (it.y_lanes_n) TTT::run(a, tile, smem);
             else TTF::run(a, tile, smem);
@@ -1376,13 +1633,13 @@ __global__ __launch_bounds__((TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, true>
 template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int L>
 struct BatchLaunch {
     static constexpr int threads = TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, true>::threads;
-    static int launch(const BatchItemDev* items, int count, int64_t total, int grid, hipStream_t s) {
+    static int launch(const BatchItemDev* items, const int32_t* off, const int32_t* ent, int grid, hipStream_t s) {
         if constexpr (L == 1) {
             set_error("batched launches use the regular and specialised-wave layouts");
             return TC_ERR_ARG;
         } else {
             hipLaunchKernelGGL((batch_kernel<T, OffT, MT, NT, KT, WM, WN, L>), dim3(grid), dim3(threads), 0, s,
-                               items, count, total);
+                               items, off, ent);
             hipError_t e = hipGetLastError();
             return e == hipSuccess ? TC_OK : hip_fail(e, "batched kernel launch");
         }
@@ -1404,11 +1661,11 @@ struct BatchLaunch {
 };
 
 template <typename T, typename OffT>
-static int batch_dispatch(int dtype, int tile, bool launch, const BatchItemDev* items, int count, int64_t total,
-                          int grid, hipStream_t s) {
-#define TC_BCASE(id, MT, NT, KT, WM, WN, L)                                                               \
-    case id:                                                                                              \
-        return launch ? BatchLaunch<T, OffT, MT, NT, KT, WM, WN, L>::launch(items, count, total, grid, s) \
+static int batch_dispatch(int dtype, int tile, bool launch, const BatchItemDev* items, const int32_t* off,
+                          const int32_t* ent, int64_t total, int grid, hipStream_t s) {
+#define TC_BCASE(id, MT, NT, KT, WM, WN, L)                                                            \
+    case id:                                                                                           \
+        return launch ? BatchLaunch<T, OffT, MT, NT, KT, WM, WN, L>::launch(items, off, ent, grid, s) \
                       : BatchLaunch<T, OffT, MT, NT, KT, WM, WN, L>::grid(total);
     (void)dtype;  // the storage type T fixes the tile table
     if constexpr (sizeof(T) == 8) {

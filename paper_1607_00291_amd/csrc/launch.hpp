@@ -35,11 +35,12 @@ struct BatchItemDev {
     int32_t kregX, kregY;  // 1: every k block of X (Y) has a nonzero block stride
 };
 
-// Launch the persistent batched kernel of tile configuration `tile` over
-// `count` problems (table on the device, ordered by first_item) covering
-// total_items work items, with `grid` workgroups.
-int launch_batch(int dtype, int mode, int tile, bool off64, const BatchItemDev* items_dev, int count,
-                 int64_t total_items, int grid, hipStream_t stream);
+// Launch the persistent batched kernel of tile configuration `tile` with
+// `grid` workgroups: workgroup g runs the work items ent[2j] (problem index
+// into items_dev) and ent[2j + 1] (tile of that problem) for j in
+// [off[g], off[g + 1]).  total_items (> 0) is the number of work items.
+int launch_batch(int dtype, int mode, int tile, bool off64, const BatchItemDev* items_dev, const int32_t* off,
+                 const int32_t* ent, int64_t total_items, int grid, hipStream_t stream);
 // Workgroups of a persistent batched launch: min(total_items, resident
 // workgroups of the tile's kernel on the current device).
 int batch_grid(int dtype, int mode, int tile, bool off64, int64_t total_items);

@@ -1,7 +1,9 @@
 // Planner: label classification into the bundles I, J, P (Sec. 4), the
-// dimension reordering heuristic (Sec. 7.3) with a GPU amendment for the P
-// order, scatter vectors (Sec. 6.1) and block strides (Sec. 6.2) at the tile
-// granularity of the GPU kernel.
+// dimension reordering heuristic (Sec. 7.3) with two GPU amendments (the P
+// order follows the operand with its unit stride in P; an operand's
+// unit-stride index goes to the front of its free bundle), scatter vectors
+// (Sec. 6.1) and block strides (Sec. 6.2) at the tile granularity of the GPU
+// kernel.
 #include "plan.hpp"
 
 #include <algorithm>
@@ -229,16 +231,45 @@ int build_plan(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, in
         for (Dim& d : J) std::swap(d.sX, d.sY);
         for (Dim& d : P) std::swap(d.sX, d.sY);
     }
-    // 5. order P.  The paper sorts by A's stride.  On the GPU each operand is
-    // gathered with its lanes along its unit-stride index, so P is sorted by
-    // the stride of whichever operand has its unit stride inside P (ties: X).
+    // 5. order P by increasing stride in A (X after the swap), as printed
+    sort_by(&P, 0);
+    auto names = [](const std::vector<Dim>& v) {
+        std::string out;
+        for (const Dim& d : v) out += d.labels;
+        return out;
+    };
+    p->paper_order = names(I) + "|" + names(J) + "|" + names(P);
+    // GPU amendment 1.  Each operand is gathered with its lanes along its
+    // unit-stride index, so P is sorted by the stride of whichever operand
+    // has its unit stride inside P (ties: X).
     bool ux = false, uy = false;
     for (const Dim& d : P) {
         ux |= d.sX == 1;
         uy |= d.sY == 1;
     }
-    int pkey = (!ux && uy) ? 1 : 0;  // 0: sort P by X stride, 1: by Y stride
-    sort_by(&P, pkey);
+    if (!ux && uy) sort_by(&P, 1);
+    // GPU amendment 2.  The C-stride sort of step 3 can leave an operand's
+    // unit-stride index behind another index of its free bundle (C and the
+    // operand order the bundle's indices differently, Sec. 7.3 and Sec. 9.3);
+    // then neither the m (n) nor the k direction of that operand is unit
+    // stride and every lane of its gather reads a separate line.  The gathers
+    // are repeated for every tile column (row) while C is written once, and
+    // the tile stores' lanes run along n in most fragment layouts, so the
+    // operand's unit-stride index is moved to the front of its free bundle.
+    auto unit_first = [](std::vector<Dim>* v, int which) {
+        for (size_t i = 1; i < v->size(); ++i) {
+            const int64_t s = which == 0 ? (*v)[i].sX : (*v)[i].sY;
+            if (s == 1) {
+                Dim d = (*v)[i];
+                v->erase(v->begin() + (long)i);
+                v->insert(v->begin(), d);
+                return 1;
+            }
+        }
+        return 0;
+    };
+    if (!(!I.empty() && I[0].sX == 1) && !(!P.empty() && P[0].sX == 1)) p->unit_moves += unit_first(&I, 0);
+    if (!(!J.empty() && J[0].sY == 1) && !(!P.empty() && P[0].sY == 1)) p->unit_moves += unit_first(&J, 1);
     // 2. fold dimensions contiguous in every tensor holding them (after the
     //    sort, so adjacency refers to the planned order)
     p->folds += fold(&I, true, false, true);
@@ -385,7 +416,8 @@ std::string describe_plan(const Plan& p) {
     os << "\"dtype\":" << p.dtype << ",\"mode\":" << p.mode << ",\"swapped\":" << (p.swapped ? "true" : "false")
        << ",\"m\":" << p.m << ",\"n\":" << p.n << ",\"k\":" << p.k << ",\"noop\":" << (p.noop ? "true" : "false")
        << ",\"k_empty\":" << (p.k_empty ? "true" : "false") << ",\"off64\":" << (p.off64 ? "true" : "false")
-       << ",\"folds\":" << p.folds << ",\"dropped\":" << p.dropped << ',';
+       << ",\"folds\":" << p.folds << ",\"dropped\":" << p.dropped << ",\"unit_moves\":" << p.unit_moves
+       << ",\"paper_order\":\"" << p.paper_order << "\",";
     json_dims(os, "I", p.I);
     json_dims(os, "J", p.J);
     json_dims(os, "P", p.P);

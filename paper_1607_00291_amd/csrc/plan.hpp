@@ -51,6 +51,8 @@ struct Plan {
     bool off64 = false;       // offsets need 64 bits
     int folds = 0;            // number of fold steps performed
     int dropped = 0;          // number of length-1 dims dropped
+    int unit_moves = 0;       // operands whose unit-stride index was moved to the front of their free bundle
+    std::string paper_order;  // "I|J|P" labels in the order of the paper's heuristic (before the GPU amendments and the fold)
 
     // scatter vectors (Sec. 6.1): rows of X and C over I, columns of Y and C
     // over J, columns of X and rows of Y over P

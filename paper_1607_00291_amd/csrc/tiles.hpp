@@ -36,7 +36,8 @@
     X(1, 64, 64, 32, 2, 2, 0)      \
     X(2, 128, 64, 32, 2, 2, 0)     \
     X(3, 128, 128, 32, 2, 2, 0)    \
-    X(4, 144, 144, 32, 3, 3, 0)
+    X(4, 144, 144, 32, 3, 3, 0)    \
+    X(5, 144, 144, 32, 1, 1, 2)
 
 namespace tc {
 
@@ -67,7 +68,8 @@ static const TileRate kRatesF64[] = {{31, 31, 2, 1},     {25, 46, 2, 1},     {35
                                      {40.6, 40.6, 1, 1}, {51.4, 51.4, 1, 1}, {54.5, 54.5, 1, 0.7}};
 static const TileRate kRatesF32[] = {{50, 54, 2, 1}, {41, 86, 2, 1}, {58, 94, 2, 1},
                                      {65, 96, 2, 1}, {94, 94, 1, 1}, {110, 110, 1, 0.7}};
-static const TileRate kRatesBF16x3[] = {{45, 50, 2, 1}, {38, 105, 2, 1}, {59, 104, 2, 1}, {76, 145, 2, 1}, {144, 144, 1, 1}};
+static const TileRate kRatesBF16x3[] = {{45, 50, 2, 1},   {38, 105, 2, 1},   {59, 104, 2, 1},
+                                        {76, 145, 2, 1},   {144, 144, 1, 1},  {140, 140, 1, 0.7}};
 static_assert(sizeof(kRatesF64) / sizeof(TileRate) == sizeof(kTilesF64) / sizeof(TileCfg), "one rate per tile");
 static_assert(sizeof(kRatesF32) / sizeof(TileRate) == sizeof(kTilesF32) / sizeof(TileCfg), "one rate per tile");
 static_assert(sizeof(kRatesBF16x3) / sizeof(TileRate) == sizeof(kTilesBF16x3) / sizeof(TileCfg), "one rate per tile");

@@ -318,3 +318,38 @@ def test_int64_offsets(oracle_mod, dtype):
             assert np.all(np.abs(got - ref) <= bound + 1e-30), f"tile {t}"
     del storage
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_unit_stride_index_not_first_in_free_bundle(oracle_mod, dtype):
+    """Layouts where C orders a free bundle differently from the operand that
+    holds it (no order gives unit stride in both, Sec. 7.3): A[u v p] B[p j]
+    -> C[v u j] (A's unit stride on u, C's on v), and B[w j p] with C[i j w]
+    (B's unit stride on w, C's order puts j first).  The planner moves the
+    operand's unit-stride index to the front of its bundle; every output is
+    compared with the oracle, beta != 0, tiles ragged in m, n and k."""
+    from paper_1607_00291_amd import tc
+    rng = np.random.default_rng(17)
+    cases = [("uvp", "pj", "vuj", {"u": 40, "v": 48, "p": 72, "j": 100}),
+             ("ip", "wjp", "ijw", {"i": 150, "p": 66, "w": 36, "j": 20})]
+    for ia, ib, ic, e in cases:
+        mk = lambda lab: inputs.colmajor_from_flat(rng.uniform(-1, 1, int(np.prod(inputs.shape_of(lab, e)))),
+                                                   inputs.shape_of(lab, e))
+        A, B, C = mk(ia), mk(ib), mk(ic)
+        if dtype == np.float32:
+            A, B, C = (np.asfortranarray(x.astype(np.float32).astype(np.float64)) for x in (A, B, C))
+        p = inputs.Problem(ia, ib, ic, A, B, C, 1.5, -0.5, f"unit-first {ia},{ib}->{ic}", e)
+        s = lambda a: [x // a.itemsize for x in a.strides]
+        d = tc.describe(A.shape, s(A), ia, B.shape, s(B), ib, C.shape, s(C), ic,
+                        tc.TC_F64 if dtype == np.float64 else tc.TC_F32)
+        assert d["unit_moves"] == 1, d["paper_order"]
+        print(f"case {p.name} {np.dtype(dtype).name} paper {d['paper_order']} lanes {d['x_lanes']}/{d['y_lanes']}",
+              flush=True)
+        got = gpu_result(p, dtype).astype(np.float64)
+        if dtype == np.float64:
+            check_fp64(oracle_mod, p, got)
+        else:
+            ref = oracle_result(oracle_mod, p)
+            absC = oracle_result(oracle_mod, inputs.Problem(ia, ib, ic, A, B, np.zeros_like(C, order="F"), 1.0, 0.0),
+                                 absval=True)
+            assert np.all(np.abs(got - ref) <= fp32_componentwise(p.mnk()[2], p.alpha, absC, p.beta, p.C) + 1e-30)

@@ -139,11 +139,16 @@ def test_scatter_vectors_address_every_element(seed):
 
 
 def test_heuristic_cfg1():
+    """The paper's heuristic orders J = (c, d) by C's strides; B[dfce] has its
+    unit stride on d, so the GPU amendment moves d to the front of J and B is
+    gathered with unit stride along n."""
     d = describe(inputs.cfg1())
     assert not d["swapped"]
+    assert d["paper_order"] == "ab|cd|ef"
     assert [x["labels"] for x in d["I"]] == ["a", "b"]
-    assert [x["labels"] for x in d["J"]] == ["c", "d"]
+    assert [x["labels"] for x in d["J"]] == ["d", "c"]
     assert [x["labels"] for x in d["P"]] == ["e", "f"]
+    assert d["unit_moves"] == 1 and d["J"][0]["sY"] == 1
     assert (d["m"], d["n"], d["k"]) == (256, 256, 256)
     assert d["x_lanes"] == "m" and d["y_lanes"] == "n"
 
@@ -153,6 +158,7 @@ def test_heuristic_cfg2_gpu_amendment():
     on c, so the amended order is P = (c, k) and T is gathered along k."""
     d = describe(inputs.cfg2())
     assert not d["swapped"]
+    assert d["paper_order"] == "ai|bj|kc" and d["unit_moves"] == 0
     assert [x["labels"] for x in d["I"]] == ["a", "i"]
     assert [x["labels"] for x in d["J"]] == ["b", "j"]
     assert [x["labels"] for x in d["P"]] == ["c", "k"]
@@ -180,6 +186,28 @@ def test_heuristic_cfg4_fold_and_backward():
     q = inputs.Problem("iklb", "ijab", "kjal", p.A, p.dC, dB, 1.0, 0.0, "dB", p.extents)
     d = describe(q)
     assert d["m"] * d["n"] == 1024 * 2048 and d["k"] == 2048
+
+
+def test_unit_stride_index_moved_to_front_of_free_bundle():
+    """A[u v p] B[p j] -> C[v u j]: C's unit stride is on v, A's on u (Sec. 7.3
+    notes that no order gives unit stride in both).  The paper's order is
+    I = (v, u); the planner moves u to the front so that A's gather lanes run
+    with unit stride (the C tile is written once; A's slivers are gathered by
+    every tile column), and the scatter vectors still address every element."""
+    e = {"u": 32, "v": 48, "p": 40, "j": 24}
+    A = inputs.colmajor((32, 48, 40))
+    B = inputs.colmajor((40, 24))
+    C = inputs.colmajor((48, 32, 24))
+    p = inputs.Problem("uvp", "pj", "vuj", A, B, C, 1.0, 0.0, "unit-first", e)
+    d = describe(p)
+    assert d["paper_order"] == "vu|j|p"
+    assert [x["labels"] for x in d["I"]] == ["u", "v"] and d["unit_moves"] == 1
+    assert d["x_lanes"] == "m" and d["I"][0]["sX"] == 1
+    # rscat_X / rscat_C still pair each m with the same (u, v)
+    rX, rC = d["rscat_X"], d["rscat_C"]
+    for m in range(0, 32 * 48, 37):
+        u, v = m % 32, m // 32
+        assert rX[m] == u + 32 * v and rC[m] == v + 48 * u
 
 
 def test_swap_when_C_unit_stride_in_J():
