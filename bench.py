@@ -21,9 +21,11 @@ same GPU: FP32 and split-BF16 at the same shape, the FP32 forward + backward of
 C[ijab] = A[iklb] B[kjal] (i,j,k,l = 32, a,b = 64), the FP64 extent-16
 contraction C[abcd] = A[aebf] B[dfce], 512 batched FP64 contractions against
 512 sequential launches, the transpose-transpose-GEMM-transpose method
-(Sec. 5, fig. TTGT) on the same GPU at the v=96/o=24 and the FP32 forward shapes, and a
-sweep of random contractions (Sec. 9.2) against plain GEMMs of the same size
-(unless --quick; --sections fp32,fwdbwd,x16,ttgt,batched,sweep picks a subset).
+(Sec. 5, fig. TTGT) on the same GPU at the v=96/o=24 and the FP32 forward
+shapes, a sweep of random contractions (Sec. 9.2) against plain GEMMs of the
+same size, and the pack and store stages alone with their HBM GB/s (unless
+--quick; --sections fp32,fwdbwd,x16,packstore,ttgt,batched,sweep picks a
+subset).
 
   --copy-calibration first runs a plain 1 GiB device copy three times in the
   same process: the reference that scales rocprofv3's HBM byte counters.
@@ -246,7 +248,8 @@ def plan_runner(tc, A, ia, B, ib, C, ic, alpha, beta, mode="native"):
     return plan, run
 
 
-SECTIONS = ("fp32", "fwdbwd", "x16", "ttgt", "batched", "sweep")
+SECTIONS = ("fp32", "fwdbwd", "x16", "packstore", "ttgt", "batched", "sweep")
+PEAK_HBM_GBPS = 8000.0
 
 
 def secondary(tc, inputs, steps, warmup, sections=SECTIONS):
@@ -258,6 +261,9 @@ def secondary(tc, inputs, steps, warmup, sections=SECTIONS):
         _fwdbwd(tc, inputs, steps, warmup, out)
     if "x16" in sections:
         _x16(tc, inputs, steps, warmup, out)
+    if "packstore" in sections:
+        out["pack_store_fp64_v96_o24"] = pack_store(tc, inputs, steps, warmup)
+        progress("pack and store stages done")
     if "ttgt" in sections:
         out["ttgt_baseline"] = ttgt_baseline(tc, inputs, steps, warmup)
         progress("TTGT baseline done")
@@ -339,6 +345,57 @@ def _x16(tc, inputs, steps, warmup, out):
     out["fp64_abcd_aebf_dfce_x16"] = {"us_per_call": round(ms * 1e3, 2), "gflops": round(p.flops() / ms / 1e6, 1)}
     plan.close()
     del A, B, C
+
+
+def pack_store(tc, inputs, steps, warmup):
+    """The contraction's pack stage (gather of W and of T into tile panels)
+    and store stage (Z := Z0 + src through the C offset vectors, beta = 1)
+    run alone at the v=96/o=24 FP64 shape with the plan's own tile, against
+    the HBM peak.  Algorithmic bytes: the operand elements gathered and the
+    panel written (pack), src and C read and C written (store), plus 4 bytes
+    per distinct offset entry each workgroup reads (a sliver's R row offsets
+    and KT k offsets; a fragment's 16 row and 16 column offsets)."""
+    import torch
+    p = inputs.cfg2()
+    W, T, Z = dev(p.A), dev(p.B), dev(p.C)
+    plan = tc.Plan.for_tensors(W, p.idx_A, T, p.idx_B, Z, p.idx_C)
+    plan.upload()
+    d = plan.describe()
+    lib, h = tc.lib(), plan.handle
+    sp = torch.cuda.current_stream().cuda_stream
+    res = {"tile": [d["MT"], d["NT"], d["KT"]]}
+    nkb = -(-d["k"] // d["KT"])
+    for operand, (src, name) in enumerate(((W, "pack_W"), (T, "pack_T"))):
+        elems = plan.pack_elements(operand)
+        dst = torch.empty(elems, dtype=torch.float64, device="cuda")
+        x = (operand == 0) != d["swapped"]
+        R = d["MT"] if x else d["NT"]
+        rows = d["m"] if x else d["n"]
+        slivers = -(-rows // R) * nkb
+        sp_, dp_ = src.data_ptr(), dst.data_ptr()
+
+        def run(op=operand, a=sp_, b=dp_):
+            tc._check(lib.tc_plan_pack(h, op, a, b, sp))
+        ms = time_calls(run, steps, warmup)
+        moved = 8 * (rows * d["k"] + elems) + 4 * slivers * (R + d["KT"])
+        res[name] = {"us": round(ms * 1e3, 2), "bytes": moved, "gbps": round(moved / ms / 1e6, 1),
+                     "frac_of_hbm_peak": round(moved / ms / 1e6 / PEAK_HBM_GBPS, 4)}
+        del dst
+    m, n = d["m"], d["n"]
+    src = torch.empty(m * n, dtype=torch.float64, device="cuda").normal_()
+    frags = d["tiles_m"] * d["tiles_n"] * (d["MT"] // 16) * (d["NT"] // 16)
+    a, b = src.data_ptr(), Z.data_ptr()
+
+    def store():
+        tc._check(lib.tc_plan_store(h, 1.0, a, 1.0, b, sp))
+    ms = time_calls(store, steps, warmup)
+    moved = 8 * 3 * m * n + 4 * 32 * frags
+    res["store_Z_beta1"] = {"us": round(ms * 1e3, 2), "bytes": moved, "gbps": round(moved / ms / 1e6, 1),
+                            "frac_of_hbm_peak": round(moved / ms / 1e6 / PEAK_HBM_GBPS, 4)}
+    plan.close()
+    del W, T, Z, src
+    torch.cuda.empty_cache()
+    return res
 
 
 def ttgt_baseline(tc, inputs, steps, warmup):

@@ -148,6 +148,34 @@ int tc_plan_upload(tc_plan* plan);
 int tc_plan_execute(const tc_plan* plan, double alpha, const void* A, const void* B, double beta, void* C,
                     void* stream);
 
+/*
+ * The pack and store stages of tc_plan_execute run alone, so that their
+ * memory traffic can be measured (the paper's scatter packing, Sec. 6.1, with
+ * the block strides of Sec. 6.2, and the scatter of the C tiles):
+ *  - tc_plan_pack gathers operand `operand` (0: the plan's A, 1: its B) from
+ *    `src` (laid out as that operand's descriptor says) with the
+ *    contraction's own gather code and writes it to `dst` as a tile-panel
+ *    matrix: with R the tile edge along the operand's free bundle (MT for the
+ *    rows m of the operand that plays X, NT for the columns n of the other),
+ *    KT the tile's k depth, r the free index (m or n) and p the contracted
+ *    index (k) in the plan's order,
+ *        dst[((r / R) * ceil(k / KT) + p / KT) * KT * R + (p % KT) * R + r % R]
+ *          = operand[element (r, p)],
+ *    and 0 in the padding past the last r and p.  tc_plan_pack_elements
+ *    gives the number of elements dst must hold (0 when k or a free extent is
+ *    0).  In TC_SPLIT_BF16X3 plans the FP32 elements are gathered unsplit.
+ *  - tc_plan_store writes an m x n column-major matrix `src` (src[i + m j],
+ *    i over the plan's I order, j over its J order) into C with the
+ *    contraction's tile store: C[rscat_C[i] + cscat_C[j]] = alpha src[i + m j]
+ *    + beta C[...] (C not read when beta = 0).
+ * Both are asynchronous on `stream`, allocate nothing once the plan's vectors
+ * are on the device, and check their data pointers as tc_plan_execute does
+ * (dst must not overlap src, C not src: TC_ERR_ALIAS).
+ */
+int tc_plan_pack_elements(const tc_plan* plan, int operand, int64_t* elems);
+int tc_plan_pack(const tc_plan* plan, int operand, const void* src, void* dst, void* stream);
+int tc_plan_store(const tc_plan* plan, double alpha, const void* src, double beta, void* C, void* stream);
+
 /* Free a plan and its device buffers (NULL is accepted).  The caller must
  * make sure no launch using the plan is still running. */
 int tc_plan_destroy(tc_plan* plan);

@@ -11,7 +11,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtc.so")
 
 SOURCES = ["kernels.hip", "k_f64_i32.hip", "k_f64_i64.hip", "k_f32_i32.hip", "k_f32_i64.hip", "permute.hip",
-           "noalloc.hip", "capi.cpp", "plan.cpp"]
+           "noalloc.hip", "packstore.hip", "capi.cpp", "plan.cpp"]
 ARCH = os.environ.get("TC_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instructions are disabled for all device code.

@@ -363,6 +363,85 @@ int tc_plan_execute(const tc_plan* plan, double alpha, const void* A, const void
     return execute(plan, alpha, A, B, beta, C, (hipStream_t)stream);
 }
 
+// Device copy of the plan's vectors for a launch on `stream` (uploaded
+// outside capture; under capture it must already be there).
+static int plan_vectors(const Plan& p, hipStream_t stream, DeviceVectors** dv) {
+    if (capturing(stream)) {
+        int dev = 0;
+        hipGetDevice(&dev);
+        if (dev < 0 || dev >= kMaxDevices || !p.dev[dev].bytes) {
+            set_error("plan vectors must be uploaded before graph capture (tc_plan_upload)");
+            return TC_ERR_CAPTURE;
+        }
+        *dv = &p.dev[dev];
+        return TC_OK;
+    }
+    return ensure_uploaded(p, dv);
+}
+
+int tc_plan_pack_elements(const tc_plan* plan, int operand, int64_t* elems) {
+    if (!plan || !elems) {
+        set_error("plan or elems is NULL");
+        return TC_ERR_NULL;
+    }
+    if (operand != 0 && operand != 1) {
+        set_error("operand must be 0 (A) or 1 (B)");
+        return TC_ERR_ARG;
+    }
+    const Plan& p = *plan->p;
+    *elems = (p.noop || p.k_empty) ? 0 : pack_elements(p, operand);
+    return TC_OK;
+}
+
+int tc_plan_pack(const tc_plan* plan, int operand, const void* src, void* dst, void* stream) {
+    int64_t elems = 0;
+    int st = tc_plan_pack_elements(plan, operand, &elems);
+    if (st) return st;
+    if (elems == 0) return TC_OK;
+    const Plan& p = *plan->p;
+    if (!src || !dst) {
+        set_error("src or dst is NULL");
+        return TC_ERR_NULL;
+    }
+    const size_t w = elt_size(p.dtype);
+    const int64_t span = operand == 0 ? p.spanA : p.spanB;
+    if (overlaps(dst, elems, src, span, w)) {
+        set_error("dst overlaps src");
+        return TC_ERR_ALIAS;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (!capturing(s) && ((st = check_device_span(src, span, w, "src")) || (st = check_device_span(dst, elems, w, "dst"))))
+        return st;
+    DeviceVectors* dv = nullptr;
+    if ((st = plan_vectors(p, s, &dv))) return st;
+    return launch_pack(p, *dv, operand, src, dst, s);
+}
+
+int tc_plan_store(const tc_plan* plan, double alpha, const void* src, double beta, void* C, void* stream) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return TC_ERR_NULL;
+    }
+    const Plan& p = *plan->p;
+    if (p.noop || p.m == 0 || p.n == 0) return TC_OK;
+    if (!src || !C) {
+        set_error("src or C is NULL");
+        return TC_ERR_NULL;
+    }
+    const size_t w = elt_size(p.dtype);
+    if (overlaps(C, p.spanC, src, p.m * p.n, w)) {
+        set_error("C overlaps src");
+        return TC_ERR_ALIAS;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int st;
+    if (!capturing(s) && ((st = check_device_span(src, p.m * p.n, w, "src")) || (st = check_device_span(C, p.spanC, w, "C"))))
+        return st;
+    DeviceVectors* dv = nullptr;
+    if ((st = plan_vectors(p, s, &dv))) return st;
+    return launch_store(p, *dv, alpha, src, beta, C, s);
+}
+
 int tc_plan_destroy(tc_plan* plan) {
     if (!plan) return TC_OK;
     free_device(plan->p.get());

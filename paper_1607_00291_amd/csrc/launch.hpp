@@ -51,6 +51,14 @@ int batch_grid(int dtype, int mode, int tile, bool off64, int64_t total_items);
 size_t noalloc_layout(const Plan& p, DeviceVectors* dv);
 int noalloc_vectors(const Plan& p, hipStream_t stream, DeviceVectors* dv);
 
+// The pack and store stages alone (packstore.hip): elements of an operand's
+// tile-panel matrix, its gather into dst, and the alpha/beta scatter-store of
+// an m x n column-major matrix into C.  Arguments already validated.
+int64_t pack_elements(const Plan& p, int operand);
+int launch_pack(const Plan& p, const DeviceVectors& dv, int operand, const void* src, void* dst, hipStream_t stream);
+int launch_store(const Plan& p, const DeviceVectors& dv, double alpha, const void* src, double beta, void* C,
+                 hipStream_t stream);
+
 // Strided permute-copy dst[i] = src[i] (element bits copied) on `stream`.
 // Arguments already validated by tc_permute.
 int launch_permute(const void* src, void* dst, int ndim, const int64_t* lens, const int64_t* src_strides,

@@ -19,7 +19,7 @@ MODES = {"native": TC_NATIVE, "split_bf16x3": TC_SPLIT_BF16X3, "split-bf16": TC_
 # every symbol include/tc.h declares
 EXPORTS = [
     "tc_contract", "tc_contract_noalloc", "tc_plan_create", "tc_plan_upload", "tc_plan_execute", "tc_plan_destroy",
-    "tc_plan_describe", "tc_tile_count", "tc_tile_info", "tc_plan_set_tile", "tc_plan_get_tile",
+    "tc_plan_describe", "tc_plan_pack_elements", "tc_plan_pack", "tc_plan_store", "tc_tile_count", "tc_tile_info", "tc_plan_set_tile", "tc_plan_get_tile",
     "tc_plan_autotune", "tc_batch_create", "tc_batch_execute", "tc_batch_destroy", "tc_batch_info",
     "tc_batch_set_tile", "tc_batch_autotune", "tc_batch_problem_tile",
     "tc_scatter_vector", "tc_block_strides", "tc_permute", "tc_status_string", "tc_last_error",
@@ -52,6 +52,9 @@ def lib():
         L.tc_plan_upload.argtypes = [_vp]
         L.tc_plan_execute.argtypes = [_vp, ctypes.c_double, _vp, _vp, ctypes.c_double, _vp, _vp]
         L.tc_plan_destroy.argtypes = [_vp]
+        L.tc_plan_pack_elements.argtypes = [_vp, ctypes.c_int, _i64p]
+        L.tc_plan_pack.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
+        L.tc_plan_store.argtypes = [_vp, ctypes.c_double, _vp, ctypes.c_double, _vp, _vp]
         L.tc_plan_describe.argtypes = [_vp, ctypes.c_char_p, ctypes.c_size_t]
         L.tc_tile_count.argtypes = [ctypes.c_int, ctypes.c_int]
         ip = ctypes.POINTER(ctypes.c_int)
@@ -178,6 +181,24 @@ class Plan:
 
     def execute_ptrs(self, A, B, C, alpha, beta, stream_ptr):
         return _check(lib().tc_plan_execute(self._h, float(alpha), A, B, float(beta), C, stream_ptr))
+
+    def pack_elements(self, operand):
+        """Elements of the tile-panel matrix of operand 0 (A) or 1 (B)."""
+        n = ctypes.c_int64()
+        _check(lib().tc_plan_pack_elements(self._h, int(operand), ctypes.byref(n)))
+        return n.value
+
+    def pack(self, operand, src, dst, stream=None):
+        """Gather operand 0 (A) or 1 (B) into the tile-panel matrix dst (the
+        contraction's pack stage alone)."""
+        _check(lib().tc_plan_pack(self._h, int(operand), _ptr(src), _ptr(dst), _stream_ptr(stream)))
+        return dst
+
+    def store(self, src, C, alpha=1.0, beta=0.0, stream=None):
+        """C[rscat_C[i] + cscat_C[j]] = alpha src[i + m j] + beta C (the
+        contraction's tile store alone; src is an m x n column-major matrix)."""
+        _check(lib().tc_plan_store(self._h, float(alpha), _ptr(src), float(beta), _ptr(C), _stream_ptr(stream)))
+        return C
 
     @property
     def tile(self):
