@@ -235,15 +235,17 @@ int tc_batch_execute(const tc_batch* batch, void* stream);
 int tc_batch_destroy(tc_batch* batch);
 /* Work-item count, the tile configuration (-1: per-problem classes) and the
  * largest persistent grid of the batch.  By default every problem runs with
- * the tile configuration the planner's cost model picks for it alone;
+ * the tile configuration the planner's cost model picks for it alone among
+ * the regular and regular-grid specialised-wave layouts (0 and 3);
  * problems of one class share one persistent launch (so a batch issues at
- * most one launch per configuration, the class with the most work
- * first), laid out in decreasing order of k (the cost of one tile) so that
- * the workgroups' static stride over the work list is balanced.  All regular
- * configurations of a dtype share KT, so each output element is summed in
- * the same order as by tc_plan_execute with any regular tile (bitwise
- * equal); the specialised-wave pinwheel (layout 2) sums its centre fragment
- * in another order. */
+ * most one launch per configuration, the class with the most work first),
+ * and each of its workgroups runs a fixed list of (problem, tile) work items
+ * built on the host longest-processing-time-first (the cost of a tile is its
+ * k plus three stages).  The regular layouts and the regular-grid
+ * specialised-wave layout of a dtype share KT and sum every output element
+ * in the same order as tc_plan_execute with any of them (bitwise equal); the
+ * specialised-wave pinwheel (layout 2) sums its centre fragment in another
+ * order. */
 int tc_batch_info(const tc_batch* batch, int64_t* work_items, int* tile, int* grid);
 /* The tile configuration problem `problem` (its index in tc_batch_create's
  * arrays) runs with under the batch's current setting, or -1 when the problem

@@ -624,11 +624,11 @@ int tc_contract_noalloc(double alpha, const void* A, int ndim_A, const int64_t* 
 
 namespace tc {
 
-// Work-item counts and prefix sums of a batch, then the table upload.  The
-// table is grouped by tile class (one persistent launch per class, the class
-// with the most work first); inside a class problems are ordered by
-// decreasing k (the cost of one tile), so that the static stride assignment
-// of the persistent kernel is balanced.
+// Work-item counts of a batch, the table upload and the workgroups' work
+// lists.  The table is grouped by tile class (one persistent launch per class,
+// the class with the most work first); inside a class problems are ordered by
+// decreasing k (the cost of one tile), the order in which the work lists
+// below hand out their tiles.
 static int batch_layout(tc_batch* b) {
     const TileCfg* tab = tile_table(b->dtype, b->mode);
     const std::vector<BatchItemDev>& items = b->host;

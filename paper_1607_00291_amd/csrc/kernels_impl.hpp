@@ -1461,6 +1461,144 @@ struct TileOf<T, OffT, MT, NT, KT, WM, WN, 2, XM, YN> {
     static constexpr int threads = 512;
 };
 
+// Specialised waves on a regular tile (layout 3): waves 0-3 (one per SIMD)
+// form a 2 x 2 grid, each owning an (MT/2) x (NT/2) block of fragments, and
+// only read LDS and issue matrix instructions; waves 4-7 (one per SIMD) do
+// every gather (4 and 5 the X sliver, 6 and 7 the Y sliver) and the LDS
+// stores.  The tile edges are free, so the output grid can be matched to the
+// 256 compute units (2048 x 2048 is exactly 256 tiles of 128 x 128, 2048 x
+// 1024 exactly 256 of 128 x 64), where the 144 pinwheel leaves CUs idle.
+template <typename T, typename OffT, int MT, int NT, int KT, bool XM, bool YN>
+struct TileWSGrid {
+    static constexpr int NTHR = 512;
+    static constexpr int FM = MT / 32, FN = NT / 32;  // fragments per compute wave
+    static_assert(MT % 32 == 0 && NT % 32 == 0, "each compute wave owns whole 16 x 16 fragments");
+    static_assert(KT % 4 == 0, "KT must be a multiple of the MFMA depth");
+    // gathered stages in flight per producer thread, within the 63 loads the
+    // memory counter tracks
+    static constexpr int EMAX = (MT > NT ? MT : NT) * KT / 128;
+    static constexpr int SLOTS = 3 * EMAX <= 63 ? 3 : 2 * EMAX <= 63 ? 2 : 1;
+    typedef PackRole<T, OffT, MT, KT, 128, SLOTS> PRX;
+    typedef PackRole<T, OffT, NT, KT, 128, SLOTS> PRY;
+    static constexpr int LDX = Pitch<MT, XM>::value, LDY = Pitch<NT, YN>::value;
+    static constexpr int XS = KT * LDX, YS = KT * LDY;
+    static constexpr int SMEM = 2 * (XS + YS);
+    typedef typename MfmaFor<T, (FN >= FM)>::type MW;
+
+    static __device__ __forceinline__ void run(const KArgs<T, OffT>& a, int64_t tile, T* smem) {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int64_t tm = tile % a.tiles_m, tn = tile / a.tiles_m;
+        const OffT m0 = (OffT)(tm * MT), n0 = (OffT)(tn * NT);
+        const OffT nkb = (a.k + KT - 1) / KT;
+        if (wave >= 4) {
+            // ---- producer waves ----
+            const bool gx = wave < 6;
+            const int tt = tid & 127;
+            auto produce = [&](auto& pk, const T* gbase, int64_t gspan, const OffT* gk, const OffT* gbs, T* gstage,
+                               int gsz, OffT ks, int kreg) {
+                OffT pre_sk = 0, pre_k = 0;
+                auto fetch = [&](OffT kb) {
+                    pre_sk = uniform(gbs[kb]);
+                    pre_k = uniform(gk[kb * KT]);
+                };
+                auto body = [&](OffT kb, auto slot, auto reg) {
+                    constexpr int SL = decltype(slot)::value;
+                    constexpr int RG = decltype(reg)::value;
+                    const int buf = (int)(kb & 1);
+                    const OffT lk = kb + SLOTS < nkb ? kb + SLOTS : nkb - 1;
+                    pk.template load_with<SL, RG>(pre_sk, pre_k, gbase, gspan, gk, lk, a.k, tt);
+                    fetch(kb + SLOTS + 1 < nkb ? kb + SLOTS + 1 : nkb - 1);
+                    pk.template store<(SL + 1) % SLOTS>(gstage + (buf ^ 1) * gsz, tt);
+                    __syncthreads();
+                };
+                auto pipeline = [&](auto reg) {
+                    constexpr int RG = decltype(reg)::value;
+                    fetch(0);
+                    pk.template load_with<0, RG>(pre_sk, pre_k, gbase, gspan, gk, 0, a.k, tt);
+                    pk.template store<0>(gstage, tt);
+                    static_for<SLOTS - 1>([&](auto ic) {
+                        constexpr int i = decltype(ic)::value + 1;
+                        fetch(nkb > i ? i : nkb - 1);
+                        pk.template load_with<i, RG>(pre_sk, pre_k, gbase, gspan, gk, nkb > i ? i : nkb - 1, a.k, tt);
+                    });
+                    fetch(nkb > SLOTS ? SLOTS : nkb - 1);
+                    __syncthreads();
+                    for (OffT kb = 0; kb < nkb; kb += SLOTS)
+                        static_for<SLOTS>([&](auto ic) { body(kb + decltype(ic)::value, ic, reg); });
+                };
+                if (nkb > 0) {
+                    if (sizeof(OffT) == 4 && ks != 0) {
+                        pk.fix_offsets(ks, a.k, tt);
+                        pipeline(std::integral_constant<int, 2>());
+                    } else if (kreg) {
+                        pipeline(std::integral_constant<int, 1>());
+                    } else {
+                        pipeline(std::integral_constant<int, 0>());
+                    }
+                }
+            };
+            if (gx) {
+                PRX pk;
+                pk.init(a.rX, m0, a.m, tt, XM, LDX);
+                produce(pk, a.X, a.spanX, a.cX, a.kbsX, smem, XS, a.ksX, a.kregX);
+            } else {
+                PRY pk;
+                pk.init(a.cY, n0, a.n, tt, YN, LDY);
+                produce(pk, a.Y, a.spanY, a.rY, a.kbsY, smem + 2 * XS, YS, a.ksY, a.kregY);
+            }
+            return;
+        }
+        // ---- compute waves ----
+        typedef typename MW::acc_t acc_t;
+        const int wm = wave & 1, wn = wave >> 1;
+        acc_t acc[FM * FN];
+#pragma unroll
+        for (int f = 0; f < FM * FN; ++f)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[f][r] = T(0);
+        const int kr0 = lane >> 4;
+        auto stage = [&](OffT kb) {
+            const int buf = (int)(kb & 1);
+            if (kb < nkb) {
+                const T* bx = smem + buf * XS + 16 * FM * wm;
+                const T* by = smem + 2 * XS + buf * YS + 16 * FN * wn;
+                typename MW::bfrag fb[FN];
+#pragma unroll
+                for (int s = 0; s < KT / 4; ++s) {
+                    const int kr = 4 * s + kr0;
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) fb[j] = MW::load_b(by + kr * LDY + 16 * j, lane);
+                    // one A fragment row at a time, the next one read over
+                    // the current row's products
+                    typename MW::afrag fa[2];
+                    fa[0] = MW::load_a(bx + kr * LDX, lane);
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) {
+                        if (i + 1 < FM) fa[(i + 1) & 1] = MW::load_a(bx + kr * LDX + 16 * (i + 1), lane);
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) MW::run(fa[i & 1], fb[j], acc[i * FN + j]);
+                    }
+                }
+            }
+            __syncthreads();
+        };
+        if (nkb > 0) {
+            __syncthreads();  // the producers' first stage
+            for (OffT kb = 0; kb < nkb; kb += SLOTS)
+#pragma unroll
+                for (int i = 0; i < SLOTS; ++i) stage(kb + i);
+        }
+        store_rect<T, OffT, MW, FM, FN, false>(a, acc, (OffT)(m0 + 16 * FM * wm), (OffT)(n0 + 16 * FN * wn), lane);
+    }
+};
+
+template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
+struct TileOf<T, OffT, MT, NT, KT, WM, WN, 3, XM, YN> {
+    typedef TileWSGrid<T, OffT, MT, NT, KT, XM, YN> type;
+    static constexpr int threads = 512;
+};
+
 template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT, bool XM, bool YN>
 __global__ __launch_bounds__((TileOf<T, OffT, MT, NT, KT, WM, WN, LAYOUT, XM, YN>::threads)) void contract_kernel(
     KArgs<T, OffT> a) {

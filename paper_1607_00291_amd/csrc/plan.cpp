@@ -364,7 +364,10 @@ int choose_tile(const Plan& p, bool batched) {
     double best_t = 1e300;
     for (int i = 0; i < nt; ++i) {
         const TileCfg& t = tab[i];
-        if (batched && t.layout == 1) continue;
+        // batches run every problem's class from one persistent kernel that
+        // holds all four lane variants of the tile; for the pinwheels that
+        // kernel spills registers, so by default batches use the other layouts
+        if (batched && (t.layout == 1 || t.layout == 2)) continue;
         const double tiles = (double)((p.m + t.MT - 1) / t.MT) * (double)((p.n + t.NT - 1) / t.NT);
         const double w = std::min((double)rate[i].occ, std::ceil(tiles / cus));
         const double rounds = std::ceil(tiles / (cus * w));

@@ -79,8 +79,9 @@ int build_plan(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, in
 // (Re)compute block strides and tile counts for plan->tile.
 void set_plan_tile(Plan* p, int tile);
 // Pick a tile configuration from the shape (wave-quantisation aware model).
-// Tile configuration of least estimated time; batched skips the layouts a
-// batched launch does not run (the all-compute pinwheel).
+// Tile configuration of least estimated time; batched skips the pinwheel
+// layouts (a batched launch does not run the all-compute one, and the
+// specialised-wave one spills registers inside the batched kernel).
 int choose_tile(const Plan& p, bool batched = false);
 // Shape signature used by the autotuner cache.
 std::string plan_signature(const Plan& p);

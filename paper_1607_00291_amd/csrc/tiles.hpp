@@ -11,7 +11,9 @@
 //            SIMD does exactly 20.25 fragments of work and 2304^2 outputs
 //            make exactly 256 tiles; 2 = the same pinwheel with specialised
 //            waves: four compute waves own one whole rectangle each, four
-//            producer waves gather both operands and do the centre
+//            producer waves gather both operands and do the centre; 3 = the
+//            specialised waves on a regular tile (a 2 x 2 grid of compute
+//            waves, four producer waves)
 #pragma once
 
 #define TC_TILES_F64(X)            \
@@ -20,7 +22,9 @@
     X(2, 128, 64, 16, 2, 2, 0)     \
     X(3, 128, 128, 16, 2, 2, 0)    \
     X(4, 144, 144, 16, 1, 1, 1)    \
-    X(5, 144, 144, 16, 1, 1, 2)
+    X(5, 144, 144, 16, 1, 1, 2)    \
+    X(6, 128, 128, 16, 2, 2, 3)    \
+    X(7, 128, 64, 16, 2, 2, 3)
 
 #define TC_TILES_F32(X)            \
     X(0, 32, 32, 32, 1, 1, 0)      \
@@ -28,7 +32,9 @@
     X(2, 128, 64, 32, 2, 2, 0)     \
     X(3, 128, 128, 32, 2, 2, 0)    \
     X(4, 144, 144, 32, 1, 1, 1)    \
-    X(5, 144, 144, 32, 1, 1, 2)
+    X(5, 144, 144, 32, 1, 1, 2)    \
+    X(6, 128, 128, 32, 2, 2, 3)    \
+    X(7, 128, 64, 32, 2, 2, 3)
 
 // split-bf16: KT is a multiple of the bf16 MFMA depth (32)
 #define TC_TILES_BF16X3(X)         \
@@ -53,9 +59,10 @@ static const TileCfg kTilesBF16x3[] = {TC_TILES_BF16X3(TC_TILE_ENTRY)};
 #undef TC_TILE_ENTRY
 
 // Measured throughput of each tile configuration on MI355X (TFLOP/s, dense
-// column-major contractions of shapes 4096^2 x 1024, 2304^3, 2048^2 x 1024
-// and 1024^2 x 4096): r1 with one workgroup per compute unit, r2 with two or
-// more resident, occ the workgroups that fit on one compute unit at once, and
+// column-major contractions of shapes 4096^2 x 1024, 2304^3, 2048^2 x 1024,
+// 2048 x 1024 x 2048 and 1024^2 x 4096): r1 with one workgroup per compute
+// unit, r2 with two or more resident, occ the workgroups that fit on one
+// compute unit at once, and
 // store the relative speed of the tile's C update (0.7 where only four of the
 // eight waves store: the output-store-bound rank-k shapes run about that much
 // slower on it).  The planner's cost model (choose_tile) is built on these.
@@ -64,10 +71,10 @@ struct TileRate {
     int occ;
     double store;
 };
-static const TileRate kRatesF64[] = {{31, 31, 2, 1},     {25, 46, 2, 1},     {35, 52, 2, 1},
-                                     {40.6, 40.6, 1, 1}, {51.4, 51.4, 1, 1}, {54.5, 54.5, 1, 0.7}};
-static const TileRate kRatesF32[] = {{50, 54, 2, 1}, {41, 86, 2, 1}, {58, 94, 2, 1},
-                                     {65, 96, 2, 1}, {94, 94, 1, 1}, {110, 110, 1, 0.7}};
+static const TileRate kRatesF64[] = {{31, 31, 2, 1},     {25, 46, 2, 1},       {35, 52, 2, 1},     {40.6, 40.6, 1, 1},
+                                     {51.4, 51.4, 1, 1}, {59.5, 59.5, 1, 0.7}, {58, 58, 1, 0.7}, {53, 58.5, 2, 0.7}};
+static const TileRate kRatesF32[] = {{50, 54, 2, 1}, {41, 86, 2, 1},       {58, 94, 2, 1},     {65, 96, 2, 1},
+                                     {94, 94, 1, 1}, {108.5, 108.5, 1, 0.7}, {104, 120, 2, 0.7}, {98.7, 110, 2, 0.7}};
 static const TileRate kRatesBF16x3[] = {{45, 50, 2, 1},   {38, 105, 2, 1},   {59, 104, 2, 1},
                                         {76, 145, 2, 1},   {144, 144, 1, 1},  {140, 140, 1, 0.7}};
 static_assert(sizeof(kRatesF64) / sizeof(TileRate) == sizeof(kTilesF64) / sizeof(TileCfg), "one rate per tile");
