@@ -162,6 +162,7 @@ struct KArgs {
     T alpha, beta;
     int kregX, kregY;  // 1: every k block of X (Y) has a nonzero block stride
     OffT ksX, ksY;     // the block stride shared by every k block of X (Y), else 0
+    int xm, yn;        // X gathered with lanes along m (else k), Y along n (else k)
 };
 
 // LDS row pitch (in elements) of a k-major stage: one element of padding when
@@ -266,6 +267,15 @@ struct PackOp {
             kbase = uniform(kvec[k0]);
 #pragma unroll
             for (int i = 0; i < E; ++i) ko[i] = (OffT)kidx(t + NTHR * i) * sk;
+        } else if (LR && NTHR % R == 0 && R % 64 == 0) {
+            // lanes along the free index, R a multiple of the wave size:
+            // element i's k is the same in every lane of a wave, so its
+            // offset is one scalar load
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const OffT kg = k0 + uniform((int32_t)kidx(t + NTHR * i));
+                ko[i] = uniform(kvec[kg < K ? kg : K - 1]);
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < E; ++i) {
@@ -565,6 +575,15 @@ struct PackRole {
             kbase = kfirst;
 #pragma unroll
             for (int i = 0; i < E; ++i) ko[i] = (OffT)kidx(t + NTHR * i) * sk;
+        } else if (lr && NTHR % R == 0 && R % 64 == 0) {
+            // lanes along the free index, R a multiple of the wave size:
+            // element i's k, (t + NTHR i) / R, is the same in every lane of a
+            // wave, so its offset is one scalar load
+#pragma unroll
+            for (int i = 0; i < E; ++i) {
+                const OffT kg = k0 + uniform((int32_t)((t + NTHR * i) / R));
+                ko[i] = uniform(kvec[kg < K ? kg : K - 1]);
+            }
         } else {
 #pragma unroll
             for (int i = 0; i < E; ++i) {
@@ -1322,8 +1341,8 @@ struct TilePinwheelWS {
             T* gstage = gx ? smem : smem + 2 * XS;
             const int gsz = gx ? XS : YS;
             PR pk;
-            if (gx) pk.init(a.rX, m0, a.m, tt, XM, LDX);
-            else pk.init(a.cY, n0, a.n, tt, YN, LDY);
+            if (gx) pk.init(a.rX, m0, a.m, tt, a.xm != 0, LDX);
+            else pk.init(a.cY, n0, a.n, tt, a.yn != 0, LDY);
             // the centre fragment: producer wave w does k-steps w - 4, w, ...
             // of every stage
             acc_t accc;
@@ -1540,11 +1559,11 @@ struct TileWSGrid {
             };
             if (gx) {
                 PRX pk;
-                pk.init(a.rX, m0, a.m, tt, XM, LDX);
+                pk.init(a.rX, m0, a.m, tt, a.xm != 0, LDX);
                 produce(pk, a.X, a.spanX, a.cX, a.kbsX, smem, XS, a.ksX, a.kregX);
             } else {
                 PRY pk;
-                pk.init(a.cY, n0, a.n, tt, YN, LDY);
+                pk.init(a.cY, n0, a.n, tt, a.yn != 0, LDY);
                 produce(pk, a.Y, a.spanY, a.rY, a.kbsY, smem + 2 * XS, YS, a.ksY, a.kregY);
             }
             return;
@@ -1679,6 +1698,8 @@ static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, co
     a.kregY = p.k_blocks_regular_y == (int64_t)p.kbsY.size();
     a.ksX = (OffT)common_stride(p.kbsX);
     a.ksY = (OffT)common_stride(p.kbsY);
+    a.xm = p.x_lanes_m;
+    a.yn = p.y_lanes_n;
     if (p.m == 0 || p.n == 0) return TC_OK;
     if (p.k_empty || p.k == 0 || alpha == 0.0) {
         int64_t total = p.m * p.n;
@@ -1757,6 +1778,8 @@ __global__ __launch_bounds__((TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, true>
         a.kregY = it.kregY;
         a.ksX = 0;  // per-tile byte offsets are not formed in batched launches
         a.ksY = 0;
+        a.xm = it.x_lanes_m;
+        a.yn = it.y_lanes_n;
         if (it.x_lanes_m) {
             if (it.y_lanes_n) TTT::run(a, tile, smem);
             else TTF::run(a, tile, smem);
