@@ -35,22 +35,28 @@ __global__ __launch_bounds__(256) void pack_kernel(const T* __restrict__ src, in
     for (int e = threadIdx.x; e < KT * R; e += 256) out[e] = stage[(e / R) * ld + e % R];
 }
 
+// One wave per 16 x 16 fragment of the tile grid (fragment f of tile t is
+// wave t * nfrag + f), four waves per workgroup: enough waves in flight to
+// cover the gather latency of the offset and C reads.
 template <typename T, typename OffT>
-__global__ __launch_bounds__(256) void store_kernel(KArgs<T, OffT> a, const T* __restrict__ src, int MT, int NT) {
+__global__ __launch_bounds__(256) void store_kernel(KArgs<T, OffT> a, const T* __restrict__ src, int MT, int NT,
+                                                    int64_t frags) {
     typedef Mfma<T> M;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t tm = blockIdx.x % a.tiles_m, tn = blockIdx.x / a.tiles_m;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= frags) return;
     const int fm = MT / 16, nfrag = fm * (NT / 16);
-    for (int f = wave; f < nfrag; f += 4) {
-        const OffT fm0 = (OffT)(tm * MT + 16 * (f % fm)), fn0 = (OffT)(tn * NT + 16 * (f / fm));
-        typename M::acc_t acc;
+    const int64_t tile = g / nfrag;
+    const int f = (int)(g - tile * nfrag);
+    const int64_t tm = tile % a.tiles_m, tn = tile / a.tiles_m;
+    const OffT fm0 = (OffT)(tm * MT + 16 * (f % fm)), fn0 = (OffT)(tn * NT + 16 * (f / fm));
+    typename M::acc_t acc;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const OffT r = fm0 + M::row(lane, t), c = fn0 + M::col(lane, t);
-            acc[t] = r < a.m && c < a.n ? src[(int64_t)r + (int64_t)a.m * c] : T(0);
-        }
-        store_frag<T, OffT, M>(a, fm0, fn0, acc, lane);
+    for (int t = 0; t < 4; ++t) {
+        const OffT r = fm0 + M::row(lane, t), c = fn0 + M::col(lane, t);
+        acc[t] = r < a.m && c < a.n ? src[(int64_t)r + (int64_t)a.m * c] : T(0);
     }
+    store_frag<T, OffT, M>(a, fm0, fn0, acc, lane);
 }
 
 template <typename T, typename OffT, int R, int KT>
@@ -116,13 +122,14 @@ int store_typed(const Plan& p, const DeviceVectors& dv, double alpha, const void
     a.tiles_n = p.tiles_n;
     a.alpha = (T)alpha;
     a.beta = (T)beta;
-    const int64_t tiles = p.tiles_m * p.tiles_n;
-    if (tiles == 0) return TC_OK;
-    if (tiles > 0x7fffffffLL) {
-        set_error("too many tiles for one launch");
+    const int64_t frags = p.tiles_m * p.tiles_n * (t.MT / 16) * (t.NT / 16), blocks = (frags + 3) / 4;
+    if (frags == 0) return TC_OK;
+    if (blocks > 0x7fffffffLL) {
+        set_error("too many fragments for one launch");
         return TC_ERR_ARG;
     }
-    hipLaunchKernelGGL((store_kernel<T, OffT>), dim3((unsigned)tiles), dim3(256), 0, s, a, (const T*)src, t.MT, t.NT);
+    hipLaunchKernelGGL((store_kernel<T, OffT>), dim3((unsigned)blocks), dim3(256), 0, s, a, (const T*)src, t.MT, t.NT,
+                       frags);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? TC_OK : hip_fail(e, "store kernel launch");
 }
