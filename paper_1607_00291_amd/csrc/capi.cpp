@@ -938,6 +938,14 @@ static int batch_create(tc_batch** out, int count, const tc_plan* const* plans, 
         it.y_lanes_n = p.y_lanes_n;
         it.kregX = p.k_blocks_regular_x == (int64_t)p.kbsX.size();
         it.kregY = p.k_blocks_regular_y == (int64_t)p.kbsY.size();
+        auto shared_stride = [](const std::vector<int64_t>& kbs) -> int64_t {
+            if (kbs.empty() || kbs[0] == 0) return 0;
+            for (int64_t v : kbs)
+                if (v != kbs[0]) return 0;
+            return kbs[0];
+        };
+        it.ksX = shared_stride(p.kbsX);
+        it.ksY = shared_stride(p.kbsY);
         b->host_of[i] = (int)b->host.size();
         b->host.push_back(it);
         b->best.push_back(choose_tile(p, true));  // layouts a batch runs

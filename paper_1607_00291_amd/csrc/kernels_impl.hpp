@@ -1776,8 +1776,8 @@ __global__ __launch_bounds__((TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, true>
         a.beta = (T)it.beta;
         a.kregX = it.kregX;
         a.kregY = it.kregY;
-        a.ksX = 0;  // per-tile byte offsets are not formed in batched launches
-        a.ksY = 0;
+        a.ksX = (OffT)it.ksX;
+        a.ksY = (OffT)it.ksY;
         a.xm = it.x_lanes_m;
         a.yn = it.y_lanes_n;
         if (it.x_lanes_m) {

@@ -33,6 +33,7 @@ struct BatchItemDev {
     double alpha, beta;
     int32_t x_lanes_m, y_lanes_n;
     int32_t kregX, kregY;  // 1: every k block of X (Y) has a nonzero block stride
+    int64_t ksX, ksY;      // the block stride shared by every k block of X (Y), else 0
 };
 
 // Launch the persistent batched kernel of tile configuration `tile` with

@@ -26,10 +26,13 @@ namespace {
 __device__ __align__(256) unsigned char scratch[TC_NOALLOC_SCRATCH_BYTES];
 
 // One vector to build: the scatter vector of a bundle (entry x = sum over
-// the bundle's dims of digit_d(x) * stride_d, first dim fastest), or, with
+// the bundle's dims of digit_d(x) * stride_d, first dim fastest; with
+// sa >= 0 the plan's sub-blocked k order over dims sa and sb), or, with
 // block > 0, the block strides of that scatter vector at blocking `block`.
 struct VecJob {
     int nd;
+    int sa, sb;      // sub-blocked dims, -1 for none
+    int64_t bx, by;  // their sub-block extents
     int64_t len[kMaxDim];
     int64_t st[kMaxDim];
     int64_t total;  // entries of the scatter vector
@@ -45,7 +48,21 @@ struct VecJobs {
 
 __device__ __forceinline__ int64_t scat_at(const VecJob& j, int64_t x) {
     int64_t off = 0;
+    if (j.sa >= 0) {
+        // bands of by values of dim sb, cut into blocks of bx values of dim
+        // sa (shorter at a ragged edge), sa fastest inside a block; the
+        // other dims outside, in order
+        const int64_t La = j.len[j.sa], Lb = j.len[j.sb], plane = La * Lb;
+        const int64_t r = x % plane;
+        x /= plane;
+        const int64_t band = r / (La * j.by), r2 = r - band * La * j.by;
+        const int64_t h = j.by < Lb - band * j.by ? j.by : Lb - band * j.by;
+        const int64_t blk = r2 / (j.bx * h), r3 = r2 - blk * j.bx * h;
+        const int64_t w = j.bx < La - blk * j.bx ? j.bx : La - blk * j.bx;
+        off = (blk * j.bx + r3 % w) * j.st[j.sa] + (band * j.by + r3 / w) * j.st[j.sb];
+    }
     for (int d = 0; d < j.nd; ++d) {
+        if (d == j.sa || d == j.sb) continue;
         const int64_t q = x / j.len[d];
         off += (x - q * j.len[d]) * j.st[d];
         x = q;
@@ -115,8 +132,12 @@ int scratch_address(void** out) {
     return TC_OK;
 }
 
-void fill(VecJob* j, const std::vector<Dim>& dims, int which, int64_t block, int64_t out) {
+void fill(VecJob* j, const std::vector<Dim>& dims, int which, int64_t block, int64_t out, const Plan* sub = nullptr) {
     j->nd = (int)dims.size();
+    j->sa = sub ? sub->sub_a : -1;
+    j->sb = sub ? sub->sub_b : -1;
+    j->bx = sub ? sub->sub_bx : 1;
+    j->by = sub ? sub->sub_by : 1;
     j->total = 1;
     for (int d = 0; d < j->nd; ++d) {
         j->len[d] = dims[(size_t)d].len;
@@ -164,13 +185,13 @@ int noalloc_vectors(const Plan& p, hipStream_t stream, DeviceVectors* dv) {
     VecJobs jobs{};
     const TileCfg& t = tile_table(p.dtype, p.mode)[p.tile];
     fill(&jobs.j[0], p.I, 0, 0, (int64_t)dv->o_rX);
-    fill(&jobs.j[1], p.P, 0, 0, (int64_t)dv->o_cX);
-    fill(&jobs.j[2], p.P, 1, 0, (int64_t)dv->o_rY);
+    fill(&jobs.j[1], p.P, 0, 0, (int64_t)dv->o_cX, &p);
+    fill(&jobs.j[2], p.P, 1, 0, (int64_t)dv->o_rY, &p);
     fill(&jobs.j[3], p.J, 1, 0, (int64_t)dv->o_cY);
     fill(&jobs.j[4], p.I, 2, 0, (int64_t)dv->o_rC);
     fill(&jobs.j[5], p.J, 2, 0, (int64_t)dv->o_cC);
-    fill(&jobs.j[6], p.P, 0, t.KT, (int64_t)dv->o_kbsX);
-    fill(&jobs.j[7], p.P, 1, t.KT, (int64_t)dv->o_kbsY);
+    fill(&jobs.j[6], p.P, 0, t.KT, (int64_t)dv->o_kbsX, &p);
+    fill(&jobs.j[7], p.P, 1, t.KT, (int64_t)dv->o_kbsY, &p);
     if (p.noop) return TC_OK;
     if (p.k_empty)  // the host plan holds no contracted vectors either
         for (int i : {1, 2, 6, 7}) jobs.j[i].total = 0;

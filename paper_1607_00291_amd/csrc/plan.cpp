@@ -91,6 +91,34 @@ void scatter_vector(const std::vector<Dim>& dims, int which, std::vector<int64_t
     }
 }
 
+void scatter_vector_sub(const std::vector<Dim>& dims, int which, int a, int b, int64_t bx, int64_t by,
+                        std::vector<int64_t>* out) {
+    int64_t total = 1;
+    for (const Dim& d : dims) total *= d.len;
+    out->assign((size_t)total, 0);
+    if (total == 0) return;
+    auto st = [which](const Dim& d) { return which == 0 ? d.sX : which == 1 ? d.sY : d.sC; };
+    const int64_t La = dims[(size_t)a].len, Lb = dims[(size_t)b].len, plane = La * Lb;
+    for (int64_t x = 0; x < total; ++x) {
+        // position inside the (a, b) plane: bands of `by` values of b, each
+        // cut into blocks of `bx` values of a (the last band and block of a
+        // ragged extent are shorter), a fastest inside a block
+        const int64_t r = x % plane;
+        int64_t rest = x / plane;
+        const int64_t band = r / (La * by), r2 = r - band * La * by;
+        const int64_t h = std::min(by, Lb - band * by);
+        const int64_t blk = r2 / (bx * h), r3 = r2 - blk * bx * h;
+        const int64_t w = std::min(bx, La - blk * bx);
+        int64_t off = (blk * bx + r3 % w) * st(dims[(size_t)a]) + (band * by + r3 / w) * st(dims[(size_t)b]);
+        for (size_t d = 0; d < dims.size(); ++d) {
+            if ((int)d == a || (int)d == b) continue;
+            off += (rest % dims[d].len) * st(dims[d]);
+            rest /= dims[d].len;
+        }
+        (*out)[(size_t)x] = off;
+    }
+}
+
 void block_strides(const int64_t* scat, int64_t len, int64_t b, int64_t* out) {
     int64_t nb = (len + b - 1) / b;
     for (int64_t i = 0; i < nb; ++i) {
@@ -276,6 +304,32 @@ int build_plan(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, in
     p->folds += fold(&J, false, true, true);
     p->folds += fold(&P, true, true, false);
 
+    // GPU amendment 3.  When X and Y have their unit strides on two
+    // different P dims (the storage orders of A and B disagree inside the
+    // contracted bundle, Sec. 7.3 and Sec. 9.2-9.3), any P order leaves one
+    // operand strided along k, and a k stage of it touches one line per
+    // element.  The k order is then sub-blocked instead (the paper's
+    // sub-division of dimensions, applied to the k loop): a stage of KT
+    // entries covers bx values of X's unit-stride dim times by values of
+    // Y's, so both operands read runs of contiguous elements.  Any order of
+    // the k sum gives the same contraction.
+    {
+        int ua = -1, ub = -1;
+        for (size_t i = 0; i < P.size(); ++i) {
+            if (P[i].sX == 1 && ua < 0) ua = (int)i;
+            if (P[i].sY == 1 && ub < 0) ub = (int)i;
+        }
+        if (ua >= 0 && ub >= 0 && ua != ub) {
+            const int64_t KT = tile_table(dtype, mode)[0].KT;
+            const int64_t bx = std::min<int64_t>(KT == 16 ? 4 : 8, P[(size_t)ua].len);
+            const int64_t by = std::max<int64_t>(1, std::min<int64_t>(KT / bx, P[(size_t)ub].len));
+            p->sub_a = ua;
+            p->sub_b = ub;
+            p->sub_bx = bx;
+            p->sub_by = by;
+        }
+    }
+
     p->I = I;
     p->J = J;
     p->P = P;
@@ -299,7 +353,10 @@ int build_plan(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, in
         scatter_vector(I, 2, &p->rC);
         scatter_vector(J, 1, &p->cY);
         scatter_vector(J, 2, &p->cC);
-        if (!p->k_empty) {
+        if (!p->k_empty && p->sub_a >= 0) {
+            scatter_vector_sub(P, 0, p->sub_a, p->sub_b, p->sub_bx, p->sub_by, &p->cX);
+            scatter_vector_sub(P, 1, p->sub_a, p->sub_b, p->sub_bx, p->sub_by, &p->rY);
+        } else if (!p->k_empty) {
             scatter_vector(P, 0, &p->cX);
             scatter_vector(P, 1, &p->rY);
         }
@@ -311,6 +368,7 @@ int build_plan(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, in
     else p->x_lanes_m = !I.empty();
     if (!J.empty() && J[0].sY == 1) p->y_lanes_n = true;
     else if (!P.empty() && P[0].sY == 1) p->y_lanes_n = false;
+    else if (p->sub_a >= 0) p->y_lanes_n = false;  // runs of Y along its unit-stride P dim
     else if (!J.empty() && !P.empty()) p->y_lanes_n = J[0].sY <= P[0].sY;
     else p->y_lanes_n = !J.empty();
 
@@ -421,6 +479,11 @@ std::string describe_plan(const Plan& p) {
        << ",\"k_empty\":" << (p.k_empty ? "true" : "false") << ",\"off64\":" << (p.off64 ? "true" : "false")
        << ",\"folds\":" << p.folds << ",\"dropped\":" << p.dropped << ",\"unit_moves\":" << p.unit_moves
        << ",\"paper_order\":\"" << p.paper_order << "\",";
+    if (p.sub_a >= 0)
+        os << "\"k_sub\":{\"a\":" << p.sub_a << ",\"b\":" << p.sub_b << ",\"bx\":" << p.sub_bx << ",\"by\":" << p.sub_by
+           << "},";
+    else
+        os << "\"k_sub\":null,";
     json_dims(os, "I", p.I);
     json_dims(os, "J", p.J);
     json_dims(os, "P", p.P);

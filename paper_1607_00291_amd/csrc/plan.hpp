@@ -53,6 +53,13 @@ struct Plan {
     int dropped = 0;          // number of length-1 dims dropped
     int unit_moves = 0;       // operands whose unit-stride index was moved to the front of their free bundle
     std::string paper_order;  // "I|J|P" labels in the order of the paper's heuristic (before the GPU amendments and the fold)
+    // Sub-blocked k order (GPU amendment 3), used when X and Y have their
+    // unit strides on two different P dims: P dims sub_a (X's) and sub_b
+    // (Y's) are walked in sub-blocks of sub_bx x sub_by (sub_a fastest, then
+    // sub_b, then the blocks along sub_a, then the bands along sub_b), the
+    // other P dims outside in P order.  sub_a = -1: plain colexicographic.
+    int sub_a = -1, sub_b = -1;
+    int64_t sub_bx = 1, sub_by = 1;
 
     // scatter vectors (Sec. 6.1): rows of X and C over I, columns of Y and C
     // over J, columns of X and rows of Y over P
@@ -89,6 +96,9 @@ std::string describe_plan(const Plan& p);
 
 // scatter / block-stride primitives (Sec. 6.1 eq. cscat-c generalised; Sec. 6.2)
 void scatter_vector(const std::vector<Dim>& dims, int which, std::vector<int64_t>* out);
+// The same over P in the sub-blocked order of a plan (sub_a >= 0).
+void scatter_vector_sub(const std::vector<Dim>& dims, int which, int a, int b, int64_t bx, int64_t by,
+                        std::vector<int64_t>* out);
 void block_strides(const int64_t* scat, int64_t len, int64_t b, int64_t* out);
 
 // thread-local error message

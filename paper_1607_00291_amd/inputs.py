@@ -190,6 +190,20 @@ def random_problem(seed, n_i=2, n_j=2, n_p=2, lo=1, hi=7, beta=0.0, alpha=1.0, i
     return Problem(ia, ib, ic, A, B, C, alpha, beta, f"random[{seed}]", ext)
 
 
+def p_conflict_problem(seed, ext=None, beta=0.0):
+    """C[i j] = A[e g f i] . B[f j e g] with every operand column-major:
+    e is A's unit-stride index and f is B's, and both are contracted, so the
+    storage orders of A and B disagree inside the contracted bundle (the
+    layouts the paper discusses with dimension sub-division).  ``ext`` maps
+    the labels e, f, g, i, j to extents."""
+    rng = np.random.default_rng(seed)
+    ext = dict(ext or {"e": 13, "g": 3, "f": 10, "i": 150, "j": 70})
+    A = _uniform(rng, "egfi", ext)
+    B = _uniform(rng, "fjeg", ext)
+    C = _uniform(rng, "ij", ext) if beta != 0.0 else colmajor(shape_of("ij", ext), fill=0.0)
+    return Problem("egfi", "fjeg", "ij", A, B, C, 1.0, beta, f"p_conflict[{seed}]", ext)
+
+
 def split_extent(rng, target, dims):
     """``dims`` extents (each >= 2) whose product is close to ``target``: the
     log of the target cut at dims - 1 uniform random points, the last extent

@@ -43,6 +43,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1607_00291_amd.build`")
+        # torch ships its own HIP runtime under the same soname as the system
+        # one that libtc.so links against.  Loaded after torch, libtc.so binds
+        # to torch's copy; loaded first, it would bring in a second runtime,
+        # and of two runtimes in one process only the first to initialise
+        # sees the GPU.  So torch is always loaded first.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         desc = [ctypes.c_int, _i64p, _i64p, ctypes.c_char_p]
         L.tc_contract.argtypes = ([ctypes.c_double, _vp] + desc + [_vp] + desc + [ctypes.c_double, _vp] + desc

@@ -7,6 +7,7 @@ beta powers of two, so one rounding on either side)."""
 import numpy as np
 import pytest
 
+import korder
 from paper_1607_00291_amd import inputs
 from gpuutil import require_gpu, to_dev, to_host
 
@@ -40,11 +41,25 @@ def bundle_labels(d, key):
     return "".join(x["labels"] for x in d[key])
 
 
+def k_columns(d, P, extents):
+    """Column of the colexicographic P matrix view holding each k of the
+    plan, in the plan's k order (sub-blocked when the plan says so)."""
+    cols = []
+    for vals in korder.p_label_values(d["P"], d["k_sub"], extents):
+        c, w = 0, 1
+        for l in P:
+            c += vals[l] * w
+            w *= extents[l]
+        cols.append(c)
+    return np.asarray(cols, dtype=np.int64)
+
+
 def problems():
     yield inputs.cfg2(v=40, o=12)
     for seed in range(3):
         yield inputs.sweep_problem(300 + seed, 300, 200, 70)
     yield inputs.random_problem(301, 2, 2, 2, lo=3, hi=17, beta=0.5)
+    yield inputs.p_conflict_problem(77)
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
@@ -64,7 +79,8 @@ def test_pack_matches_matrix_view(dtype):
             for operand, (T, lab) in enumerate(((p.A, p.idx_A), (p.B, p.idx_B))):
                 x = (operand == 0) != d["swapped"]
                 rows, R = (I, d["MT"]) if x else (J, d["NT"])
-                want = panels(matrix_view(np.asarray(T, dtype=dtype), lab, rows, P), R, d["KT"])
+                M = matrix_view(np.asarray(T, dtype=dtype), lab, rows, P)
+                want = panels(M[:, k_columns(d, P, p.extents)], R, d["KT"])
                 dst = torch.full((plan.pack_elements(operand),), float("nan"), dtype=A.dtype, device="cuda")
                 print(f"case pack {p.name} {np.dtype(dtype).name} tile {tile} operand {operand} rows {rows} k {P}",
                       flush=True)

@@ -353,3 +353,33 @@ def test_unit_stride_index_not_first_in_free_bundle(oracle_mod, dtype):
             absC = oracle_result(oracle_mod, inputs.Problem(ia, ib, ic, A, B, np.zeros_like(C, order="F"), 1.0, 0.0),
                                  absval=True)
             assert np.all(np.abs(got - ref) <= fp32_componentwise(p.mnk()[2], p.alpha, absC, p.beta, p.C) + 1e-30)
+
+
+@pytest.mark.parametrize("ext", [{"e": 13, "g": 3, "f": 10, "i": 150, "j": 70},
+                                 {"e": 16, "g": 1, "f": 8, "i": 97, "j": 129},
+                                 {"e": 5, "g": 7, "f": 37, "i": 33, "j": 300},
+                                 {"e": 2, "g": 2, "f": 3, "i": 17, "j": 9}])
+def test_unit_strides_disagree_in_contracted_bundle_every_tile(oracle_mod, ext):
+    """A[e g f i] . B[f j e g] -> C[i j]: A's unit-stride index e and B's f
+    are both contracted, so the plan walks k in sub-blocks over (e, f) (the
+    layouts of Sec. 7.3 and Sec. 9.2 that call for dimension sub-division).
+    Every output against the oracle, beta != 0, every FP64 and FP32 tile,
+    extents ragged against the sub-blocks and the tiles."""
+    from paper_1607_00291_amd import tc
+    p = inputs.p_conflict_problem(31, ext, beta=0.5)
+    s = lambda a: [x // a.itemsize for x in a.strides]
+    d = tc.describe(p.A.shape, s(p.A), p.idx_A, p.B.shape, s(p.B), p.idx_B, p.C.shape, s(p.C), p.idx_C)
+    assert d["k_sub"] is not None, d["P"]
+    for t in range(tc.tile_count(tc.TC_F64)):
+        print(f"case p-conflict fp64 {ext} tile={t}", flush=True)
+        check_fp64(oracle_mod, p, gpu_result(p, tile=t))
+    q = inputs.Problem(p.idx_A, p.idx_B, p.idx_C, *(np.asfortranarray(x.astype(np.float32).astype(np.float64))
+                                                      for x in (p.A, p.B, p.C)), p.alpha, p.beta, p.name, p.extents)
+    ref = oracle_result(oracle_mod, q)
+    absC = oracle_result(oracle_mod, inputs.Problem(q.idx_A, q.idx_B, q.idx_C, q.A, q.B,
+                                                    np.zeros_like(q.C, order="F"), 1.0, 0.0), absval=True)
+    bound = fp32_componentwise(q.mnk()[2], q.alpha, absC, q.beta, q.C)
+    for t in range(tc.tile_count(tc.TC_F32)):
+        print(f"case p-conflict fp32 {ext} tile={t}", flush=True)
+        got = gpu_result(q, np.float32, tile=t).astype(np.float64)
+        assert np.all(np.abs(got - ref) <= bound + 1e-30), f"tile {t}"

@@ -103,3 +103,20 @@ def test_cfg3_fp32_and_split_error_report(oracle_mod, shape):
         ratio = np.max(err / np.maximum(bound, 1e-300))
         print(f"{shape} {mode}: max|err| vs oracle {np.max(err):.3e}, max err/bound {ratio:.3e}, "
               f"max rel err vs FP64 inputs {rel:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_split_unit_strides_disagree_in_contracted_bundle(oracle_mod, seed):
+    """Split-BF16 under the sub-blocked k order (A[e g f i] . B[f j e g]),
+    every split tile, beta != 0, within the split componentwise bound."""
+    from paper_1607_00291_amd import tc
+    ext = {"e": 13, "g": 3, "f": 10, "i": 150, "j": 70} if seed == 41 else {"e": 6, "g": 5, "f": 9, "i": 61, "j": 145}
+    p0 = inputs.p_conflict_problem(seed, ext, beta=-0.5)
+    p = inputs.Problem(p0.idx_A, p0.idx_B, p0.idx_C, f32(p0.A), f32(p0.B), f32(p0.C), 1.0, -0.5, p0.name, ext)
+    ref = oracle(oracle_mod, p)
+    absC = oracle(oracle_mod, p, absval=True, C=np.zeros_like(p.C, order="F"))
+    bound = split_bf16_componentwise(p.mnk()[2], 1.0, absC, -0.5, p.C)
+    for t in range(tc.tile_count(tc.TC_F32, tc.TC_SPLIT_BF16X3)):
+        print(f"case split p-conflict seed={seed} tile={t}", flush=True)
+        got = run(p, "split_bf16x3", tile=t)
+        assert np.all(np.abs(got - ref) <= bound + 1e-30), t

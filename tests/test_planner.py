@@ -10,6 +10,7 @@ import re
 import numpy as np
 import pytest
 
+import korder
 from paper_1607_00291_amd import inputs, tc
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -126,7 +127,8 @@ def test_scatter_vectors_address_every_element(seed):
     def off(arr, labels, vals):
         return sum(vals[l] * s for l, s in zip(labels, strides_of(arr)) if l in vals)
 
-    Iv, Jv, Pv = walk(d["I"]), walk(d["J"]), walk(d["P"])
+    Iv, Jv = walk(d["I"]), walk(d["J"])
+    Pv = korder.p_label_values(d["P"], d["k_sub"], p.extents)
     for mi, a in enumerate(Iv):
         assert d["rscat_X"][mi] == off(X, ix, a)
         assert d["rscat_C"][mi] == off(p.C, p.idx_C, a)
@@ -208,6 +210,56 @@ def test_unit_stride_index_moved_to_front_of_free_bundle():
     for m in range(0, 32 * 48, 37):
         u, v = m % 32, m // 32
         assert rX[m] == u + 32 * v and rC[m] == v + 48 * u
+
+
+@pytest.mark.parametrize("dtype", [tc.TC_F64, tc.TC_F32])
+@pytest.mark.parametrize("ext", [(7, 5, 3), (8, 8, 2), (2, 9, 1), (13, 3, 4)])
+def test_sub_blocked_k_order_when_unit_strides_disagree_in_P(dtype, ext):
+    """A[e g f i] and B[f j e g] (e unit-stride in A, f in B, both contracted):
+    no P order makes both operands contiguous along k, so the plan walks k in
+    sub-blocks over (e, f) (GPU amendment 3).  The description states the
+    sub-blocks; the k vectors address exactly the elements of that order
+    (checked against the tensors' own strides), and each (e, f, g) appears
+    once; every KT-sized k stage of either operand then reads runs of at
+    least min(4, extent) contiguous elements."""
+    ne, nf, ng = ext
+    ni, nj = 6, 5
+    A = np.zeros((ne, ng, nf, ni), order="F")
+    B = np.zeros((nf, nj, ne, ng), order="F")
+    C = np.zeros((ni, nj), order="F")
+    d = tc.describe(A.shape, strides_of(A), "egfi", B.shape, strides_of(B), "fjeg", C.shape, strides_of(C), "ij",
+                    dtype=dtype)
+    P = d["P"]
+    labs = "".join(x["labels"] for x in P)
+    ks = d["k_sub"]
+    if ne == 1 or nf == 1:
+        return
+    assert ks is not None, d
+    assert P[ks["a"]]["labels"][0] == "e" and P[ks["b"]]["labels"][0] == "f"
+    La, Lb = P[ks["a"]]["len"], P[ks["b"]]["len"]  # e and f, possibly folded with g
+    assert ks["bx"] * ks["by"] <= d["KT"] and ks["bx"] == min(4 if dtype == tc.TC_F64 else 8, La)
+    assert d["x_lanes"] == "k" and d["y_lanes"] == "k"
+    ext_of = {"e": ne, "f": nf, "g": ng}
+    vals = korder.p_label_values(P, ks, ext_of)
+    assert sorted((v["e"], v["f"], v.get("g", 0)) for v in vals) == sorted(
+        itertools.product(range(ne), range(nf), range(ng)))
+    sa, sb = strides_of(A), strides_of(B)
+    for kp, v in enumerate(vals):
+        assert d["cscat_X"][kp] == v["e"] * sa[0] + v.get("g", 0) * sa[1] + v["f"] * sa[2]
+        assert d["rscat_Y"][kp] == v["f"] * sb[0] + v["e"] * sb[2] + v.get("g", 0) * sb[3]
+    # contiguous runs inside each k stage, for both operands, where the
+    # sub-blocks tile the plane exactly and fill a stage
+    KT = d["KT"]
+    if La % ks["bx"] or Lb % ks["by"] or ks["bx"] * ks["by"] != KT:
+        return
+    for vec, run in ((d["cscat_X"], ks["bx"]), (d["rscat_Y"], ks["by"])):
+        for s0 in range(0, len(vec), KT):
+            stage = sorted(vec[s0:s0 + KT])
+            longest, cur = 1, 1
+            for x, y in zip(stage, stage[1:]):
+                cur = cur + 1 if y == x + 1 else 1
+                longest = max(longest, cur)
+            assert longest >= min(run, len(stage)), (labs, s0, stage)
 
 
 def test_swap_when_C_unit_stride_in_J():

@@ -28,7 +28,10 @@ def both(p, dtype, mode="native"):
 def test_noalloc_matches_contract_large_then_small(dtype, mode):
     big = inputs.cfg2()
     small = inputs.random_problem(8100, 2, 2, 2, lo=3, hi=17, beta=0.5, alpha=1.25)
-    for p in (big, small):
+    # unit strides of A and B on different contracted indices: the device
+    # builds the sub-blocked k order of the plan
+    conflict = inputs.p_conflict_problem(8102, {"e": 13, "g": 3, "f": 10, "i": 40, "j": 30}, beta=0.5)
+    for p in (big, small, conflict):
         print(f"case noalloc {np.dtype(dtype).name} {mode} {p.name} mnk={p.mnk()}", flush=True)
         ref, got = both(p, dtype, mode)
         assert np.array_equal(ref, got), p.name
