@@ -410,7 +410,8 @@ void set_plan_tile(Plan* p, int tile) {
 // bounded below by the time to stream every tile's A and B slivers from the
 // caches (small tiles re-read the operands many times), plus the C update of
 // each round at the tile's relative store speed (what decides short-k,
-// output-bound shapes).  Earlier tiles win ties.
+// output-bound shapes).  For a problem of a batch the rounds are fractional
+// (the other problems fill the chip).  Earlier tiles win ties.
 int choose_tile(const Plan& p, bool batched) {
     const TileCfg* tab = tile_table(p.dtype, p.mode);
     const TileRate* rate = rate_table(p.dtype, p.mode);
@@ -427,8 +428,11 @@ int choose_tile(const Plan& p, bool batched) {
         // kernel spills registers, so by default batches use the other layouts
         if (batched && (t.layout == 1 || t.layout == 2)) continue;
         const double tiles = (double)((p.m + t.MT - 1) / t.MT) * (double)((p.n + t.NT - 1) / t.NT);
-        const double w = std::min((double)rate[i].occ, std::ceil(tiles / cus));
-        const double rounds = std::ceil(tiles / (cus * w));
+        // a batch keeps every CU at the tile's full residency with the tiles
+        // of all its problems, so a problem's share is its padded work at that
+        // rate, with no rounding to waves of the chip
+        const double w = batched ? (double)rate[i].occ : std::min((double)rate[i].occ, std::ceil(tiles / cus));
+        const double rounds = batched ? tiles / (cus * w) : std::ceil(tiles / (cus * w));
         const double r = (w >= 2.0 ? rate[i].r2 : rate[i].r1) * 1e12 / cus;  // flop/s of one CU
         const double compute = rounds * w * 2.0 * t.MT * t.NT * k / r;
         const double stream = tiles * (double)(t.MT + t.NT) * k * esize / cache_bw;
