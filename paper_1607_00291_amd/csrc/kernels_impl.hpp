@@ -1493,10 +1493,14 @@ struct TileWSGrid {
     static constexpr int FM = MT / 32, FN = NT / 32;  // fragments per compute wave
     static_assert(MT % 32 == 0 && NT % 32 == 0, "each compute wave owns whole 16 x 16 fragments");
     static_assert(KT % 4 == 0, "KT must be a multiple of the MFMA depth");
-    // gathered stages in flight per producer thread, within the 63 loads the
-    // memory counter tracks
+    // gathered stages in flight per producer thread, about within the 63
+    // loads the memory counter tracks (two stages of 32 loads, one past it,
+    // measured faster for the FP32 128 x 64 tile with 32-bit offsets; the
+    // 128 x 128 FP32 tile and 64-bit offsets spill registers with two)
     static constexpr int EMAX = (MT > NT ? MT : NT) * KT / 128;
-    static constexpr int SLOTS = 3 * EMAX <= 63 ? 3 : 2 * EMAX <= 63 ? 2 : 1;
+    static constexpr int SLOTS = 3 * EMAX <= 63                                                   ? 3
+                                 : (2 * EMAX <= 64 && MT * NT <= 128 * 64 && sizeof(OffT) == 4) ? 2
+                                                                                                 : 1;
     typedef PackRole<T, OffT, MT, KT, 128, SLOTS> PRX;
     typedef PackRole<T, OffT, NT, KT, 128, SLOTS> PRY;
     static constexpr int LDX = Pitch<MT, XM>::value, LDY = Pitch<NT, YN>::value;

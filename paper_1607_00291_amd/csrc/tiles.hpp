@@ -65,7 +65,8 @@ static const TileCfg kTilesBF16x3[] = {TC_TILES_BF16X3(TC_TILE_ENTRY)};
 // compute unit at once, and
 // store the relative speed of the tile's C update (0.7 where only four of the
 // eight waves store: the output-store-bound rank-k shapes run about that much
-// slower on it).  The planner's cost model (choose_tile) is built on these.
+// slower on it).  The planner's cost model (choose_tile) is built on these;
+// on those five shapes it picks the fastest measured tile of each dtype.
 struct TileRate {
     double r1, r2;
     int occ;
@@ -73,8 +74,8 @@ struct TileRate {
 };
 static const TileRate kRatesF64[] = {{31, 31, 2, 1},     {25, 46, 2, 1},       {35, 52, 2, 1},     {40.6, 40.6, 1, 1},
                                      {51.4, 51.4, 1, 1}, {59.5, 59.5, 1, 0.7}, {58, 58, 1, 0.7}, {53, 58.5, 2, 0.7}};
-static const TileRate kRatesF32[] = {{50, 54, 2, 1}, {41, 86, 2, 1},       {58, 94, 2, 1},     {65, 96, 2, 1},
-                                     {94, 94, 1, 1}, {108.5, 108.5, 1, 0.7}, {104, 120, 2, 0.7}, {98.7, 110, 2, 0.7}};
+static const TileRate kRatesF32[] = {{50, 57, 2, 1}, {41, 88, 2, 1},       {55, 84, 2, 1},   {68, 94, 2, 1},
+                                     {94, 94, 1, 1}, {108.5, 108.5, 1, 0.7}, {83, 85, 2, 0.7}, {90, 90, 1, 0.7}};
 static const TileRate kRatesBF16x3[] = {{45, 50, 2, 1},   {38, 105, 2, 1},   {59, 104, 2, 1},
                                         {76, 145, 2, 1},   {144, 144, 1, 1},  {140, 140, 1, 0.7}};
 static_assert(sizeof(kRatesF64) / sizeof(TileRate) == sizeof(kTilesF64) / sizeof(TileCfg), "one rate per tile");
