@@ -312,17 +312,21 @@ int build_plan(const TensorDesc& A, const TensorDesc& B, const TensorDesc& C, in
     // sub-division of dimensions, applied to the k loop): a stage of KT
     // entries covers bx values of X's unit-stride dim times by values of
     // Y's, so both operands read runs of contiguous elements.  Any order of
-    // the k sum gives the same contraction.
+    // the k sum gives the same contraction.  Sub-blocks shorten X's runs
+    // along k, so they are used only when Y's best plain gather (lanes along
+    // J[0] or P[0]) has a stride longer than the run the sub-blocks give Y.
     {
         int ua = -1, ub = -1;
         for (size_t i = 0; i < P.size(); ++i) {
             if (P[i].sX == 1 && ua < 0) ua = (int)i;
             if (P[i].sY == 1 && ub < 0) ub = (int)i;
         }
-        if (ua >= 0 && ub >= 0 && ua != ub) {
-            const int64_t KT = tile_table(dtype, mode)[0].KT;
-            const int64_t bx = std::min<int64_t>(KT == 16 ? 4 : 8, P[(size_t)ua].len);
-            const int64_t by = std::max<int64_t>(1, std::min<int64_t>(KT / bx, P[(size_t)ub].len));
+        const int64_t KT = tile_table(dtype, mode)[0].KT;
+        const int64_t bx = ua >= 0 ? std::min<int64_t>(KT == 16 ? 4 : 8, P[(size_t)ua].len) : 1;
+        const int64_t by = ub >= 0 ? std::max<int64_t>(1, std::min<int64_t>(KT / bx, P[(size_t)ub].len)) : 1;
+        int64_t ybest = P.empty() ? 0 : P[0].sY;
+        if (!J.empty() && (ybest == 0 || J[0].sY < ybest)) ybest = J[0].sY;
+        if (ua >= 0 && ub >= 0 && ua != ub && ybest > by) {
             p->sub_a = ua;
             p->sub_b = ub;
             p->sub_bx = bx;

@@ -234,10 +234,20 @@ def test_sub_blocked_k_order_when_unit_strides_disagree_in_P(dtype, ext):
     ks = d["k_sub"]
     if ne == 1 or nf == 1:
         return
+    # sub-blocks only when B's best plain gather (along J[0] or P[0]) is
+    # strided by more than the run the sub-blocks would give it
+    ia = next(i for i, x in enumerate(P) if x["sX"] == 1)
+    ib = next(i for i, x in enumerate(P) if x["sY"] == 1)
+    La, Lb = P[ia]["len"], P[ib]["len"]  # e and f, possibly folded with g
+    bx = min(4 if dtype == tc.TC_F64 else 8, La)
+    by = min(d["KT"] // bx, Lb)
+    ybest = min(x for x in (d["J"][0]["sY"], P[0]["sY"]) if x > 0)
+    if ybest <= by:
+        assert ks is None, d
+        return
     assert ks is not None, d
+    assert (ks["a"], ks["b"], ks["bx"], ks["by"]) == (ia, ib, bx, by)
     assert P[ks["a"]]["labels"][0] == "e" and P[ks["b"]]["labels"][0] == "f"
-    La, Lb = P[ks["a"]]["len"], P[ks["b"]]["len"]  # e and f, possibly folded with g
-    assert ks["bx"] * ks["by"] <= d["KT"] and ks["bx"] == min(4 if dtype == tc.TC_F64 else 8, La)
     assert d["x_lanes"] == "k" and d["y_lanes"] == "k"
     ext_of = {"e": ne, "f": nf, "g": ng}
     vals = korder.p_label_values(P, ks, ext_of)
