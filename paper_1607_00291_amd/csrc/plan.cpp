@@ -415,7 +415,8 @@ void set_plan_tile(Plan* p, int tile) {
 // caches (small tiles re-read the operands many times), plus the C update of
 // each round at the tile's relative store speed (what decides short-k,
 // output-bound shapes).  For a problem of a batch the rounds are fractional
-// (the other problems fill the chip).  Earlier tiles win ties.
+// (the other problems fill the chip).  Among tiles bound by the stream term
+// the faster computing one wins; earlier tiles win exact ties.
 int choose_tile(const Plan& p, bool batched) {
     const TileCfg* tab = tile_table(p.dtype, p.mode);
     const TileRate* rate = rate_table(p.dtype, p.mode);
@@ -441,7 +442,9 @@ int choose_tile(const Plan& p, bool batched) {
         const double compute = rounds * w * 2.0 * t.MT * t.NT * k / r;
         const double stream = tiles * (double)(t.MT + t.NT) * k * esize / cache_bw;
         const double store = rounds * w * cus * (double)t.MT * t.NT * esize / (hbm_bw * rate[i].store);
-        const double time = std::max(compute, stream) + store;
+        // where the streaming bound decides, the tile that computes faster
+        // wins the tie
+        const double time = std::max(compute, stream) + store + 0.01 * compute;
         if (time < best_t * 0.999) {
             best_t = time;
             best = i;

@@ -24,7 +24,8 @@
     X(4, 144, 144, 16, 1, 1, 1)    \
     X(5, 144, 144, 16, 1, 1, 2)    \
     X(6, 128, 128, 16, 2, 2, 3)    \
-    X(7, 128, 64, 16, 2, 2, 3)
+    X(7, 128, 64, 16, 2, 2, 3)     \
+    X(8, 32, 32, 16, 2, 2, 0)
 
 #define TC_TILES_F32(X)            \
     X(0, 32, 32, 32, 1, 1, 0)      \
@@ -34,7 +35,8 @@
     X(4, 144, 144, 32, 1, 1, 1)    \
     X(5, 144, 144, 32, 1, 1, 2)    \
     X(6, 128, 128, 32, 2, 2, 3)    \
-    X(7, 128, 64, 32, 2, 2, 3)
+    X(7, 128, 64, 32, 2, 2, 3)     \
+    X(8, 32, 32, 32, 2, 2, 0)
 
 // split-bf16: KT is a multiple of the bf16 MFMA depth (32)
 #define TC_TILES_BF16X3(X)         \
@@ -65,17 +67,22 @@ static const TileCfg kTilesBF16x3[] = {TC_TILES_BF16X3(TC_TILE_ENTRY)};
 // compute unit at once, and
 // store the relative speed of the tile's C update (0.7 where only four of the
 // eight waves store: the output-store-bound rank-k shapes run about that much
-// slower on it).  The planner's cost model (choose_tile) is built on these;
-// on those five shapes it picks the fastest measured tile of each dtype.
+// slower on it).  The 32 x 32 tile on four waves (id 8) is rated from small
+// contractions (256^3 to 768^3, where it is the fastest), its large-shape
+// rate being below the larger tiles' anyway.  The planner's cost model
+// (choose_tile) is built on these; on the five large shapes it picks the
+// fastest measured tile of each dtype, on the small ones tile 8.
 struct TileRate {
     double r1, r2;
     int occ;
     double store;
 };
 static const TileRate kRatesF64[] = {{31, 31, 2, 1},     {25, 46, 2, 1},       {35, 52, 2, 1},     {40.6, 40.6, 1, 1},
-                                     {51.4, 51.4, 1, 1}, {59.5, 59.5, 1, 0.7}, {58, 58, 1, 0.7}, {53, 58.5, 2, 0.7}};
+                                     {51.4, 51.4, 1, 1}, {59.5, 59.5, 1, 0.7}, {58, 58, 1, 0.7}, {53, 58.5, 2, 0.7},
+                                     {42, 42, 1, 1}};
 static const TileRate kRatesF32[] = {{50, 57, 2, 1}, {41, 88, 2, 1},       {55, 84, 2, 1},   {68, 94, 2, 1},
-                                     {94, 94, 1, 1}, {108.5, 108.5, 1, 0.7}, {83, 85, 2, 0.7}, {90, 90, 1, 0.7}};
+                                     {94, 94, 1, 1}, {108.5, 108.5, 1, 0.7}, {83, 85, 2, 0.7}, {90, 90, 1, 0.7},
+                                     {62, 62, 1, 1}};
 static const TileRate kRatesBF16x3[] = {{45, 50, 2, 1},   {38, 105, 2, 1},   {59, 104, 2, 1},
                                         {76, 145, 2, 1},   {144, 144, 1, 1},  {140, 140, 1, 0.7}};
 static_assert(sizeof(kRatesF64) / sizeof(TileRate) == sizeof(kTilesF64) / sizeof(TileCfg), "one rate per tile");
