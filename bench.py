@@ -53,12 +53,21 @@ KERNEL_SOURCES = ("kernels_impl.hpp", "tiles.hpp", "launch.hpp", "plan.hpp", "ke
                   "k_f64_i64.hip", "k_f32_i32.hip", "k_f32_i64.hip", "plan.cpp")
 
 
+def _code_only(text):
+    """C++ source without its comments and blank lines (the hash below
+    follows the code, not its commentary)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1607_00291_amd", "csrc")
     for f in KERNEL_SOURCES:
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(d, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
