@@ -233,6 +233,40 @@ int tc_batch_create(tc_batch** batch, int count, const tc_plan* const* plans, co
                     const void* const* A, const void* const* B, const double* beta, void* const* C);
 int tc_batch_execute(const tc_batch* batch, void* stream);
 int tc_batch_destroy(tc_batch* batch);
+
+/* One problem of tc_contract_batched: the arguments of tc_contract, with the
+ * same meaning, layout and ownership. */
+typedef struct tc_problem {
+    double alpha;
+    const void* A;
+    int ndim_A;
+    const int64_t* lens_A;
+    const int64_t* strides_A;
+    const char* idx_A;
+    const void* B;
+    int ndim_B;
+    const int64_t* lens_B;
+    const int64_t* strides_B;
+    const char* idx_B;
+    double beta;
+    void* C;
+    int ndim_C;
+    const int64_t* lens_C;
+    const int64_t* strides_C;
+    const char* idx_C;
+} tc_problem;
+
+/* One-shot batched contraction (the definition of Sec. 4 for each problem):
+ * plans every problem through the same plan cache as tc_contract, builds a
+ * batch of them (as tc_batch_create), runs it on `stream` (as
+ * tc_batch_execute), waits for the stream and frees the batch.  Synchronous,
+ * and it allocates and uploads the batch tables on every call: for repeated
+ * batches or graph capture, build a batch once with tc_batch_create and
+ * replay tc_batch_execute.  count = 0 does nothing; TC_ERR_NULL for a NULL
+ * problem array with count > 0, TC_ERR_ARG for count < 0; otherwise the
+ * checks and errors of tc_contract and tc_batch_create (mixed dtypes cannot
+ * occur: dtype and mode apply to every problem). */
+int tc_contract_batched(int count, const tc_problem* problems, int dtype, int mode, void* stream);
 /* Work-item count, the tile configuration (-1: per-problem classes) and the
  * largest persistent grid of the batch.  By default every problem runs with
  * the tile configuration the planner's cost model picks for it alone among

@@ -984,6 +984,54 @@ int tc_batch_create(tc_batch** batch, int count, const tc_plan* const* plans, co
     }
 }
 
+int tc_contract_batched(int count, const tc_problem* probs, int dtype, int mode, void* stream) {
+    try {
+        if (count < 0) {
+            set_error("count < 0");
+            return TC_ERR_ARG;
+        }
+        if (count == 0) return TC_OK;
+        if (!probs) {
+            set_error("problems is NULL");
+            return TC_ERR_NULL;
+        }
+        std::vector<const tc_plan*> plans((size_t)count);
+        std::vector<double> alpha((size_t)count), beta((size_t)count);
+        std::vector<const void*> A((size_t)count), B((size_t)count);
+        std::vector<void*> C((size_t)count);
+        for (int i = 0; i < count; ++i) {
+            const tc_problem& q = probs[i];
+            tc_plan* plan = nullptr;
+            int st = cached_plan(g_plans, q.ndim_A, q.lens_A, q.strides_A, q.idx_A, q.ndim_B, q.lens_B, q.strides_B,
+                                 q.idx_B, q.ndim_C, q.lens_C, q.strides_C, q.idx_C, dtype, mode, &plan);
+            if (st) {
+                set_error("problem " + std::to_string(i) + ": " + last_error());
+                return st;
+            }
+            plans[(size_t)i] = plan;
+            alpha[(size_t)i] = q.alpha;
+            beta[(size_t)i] = q.beta;
+            A[(size_t)i] = q.A;
+            B[(size_t)i] = q.B;
+            C[(size_t)i] = q.C;
+        }
+        tc_batch* b = nullptr;
+        int st = batch_create(&b, count, plans.data(), alpha.data(), A.data(), B.data(), beta.data(), C.data());
+        if (st) return st;
+        st = tc_batch_execute(b, stream);
+        const hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        tc_batch_destroy(b);
+        if (st) return st;
+        return e == hipSuccess ? TC_OK : hipfail(e, "hipStreamSynchronize after the batch");
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory");
+        return TC_ERR_NOMEM;
+    } catch (...) {
+        set_error("internal error in the batched contraction");
+        return TC_ERR_ARG;
+    }
+}
+
 int tc_batch_execute(const tc_batch* batch, void* stream) {
     if (!batch) {
         set_error("batch is NULL");

@@ -21,7 +21,7 @@ EXPORTS = [
     "tc_contract", "tc_contract_noalloc", "tc_plan_create", "tc_plan_upload", "tc_plan_execute", "tc_plan_destroy",
     "tc_plan_describe", "tc_plan_pack_elements", "tc_plan_pack", "tc_plan_store", "tc_tile_count", "tc_tile_info", "tc_plan_set_tile", "tc_plan_get_tile",
     "tc_plan_autotune", "tc_batch_create", "tc_batch_execute", "tc_batch_destroy", "tc_batch_info",
-    "tc_batch_set_tile", "tc_batch_autotune", "tc_batch_problem_tile",
+    "tc_batch_set_tile", "tc_batch_autotune", "tc_batch_problem_tile", "tc_contract_batched",
     "tc_scatter_vector", "tc_block_strides", "tc_permute", "tc_status_string", "tc_last_error",
 ]
 
@@ -35,6 +35,15 @@ class TCError(RuntimeError):
 _lib = None
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _vp = ctypes.c_void_p
+
+
+class _Problem(ctypes.Structure):
+    """One problem of tc_contract_batched (the arguments of tc_contract)."""
+    _fields_ = [("alpha", ctypes.c_double),
+                ("A", _vp), ("ndim_A", ctypes.c_int), ("lens_A", _i64p), ("strides_A", _i64p), ("idx_A", ctypes.c_char_p),
+                ("B", _vp), ("ndim_B", ctypes.c_int), ("lens_B", _i64p), ("strides_B", _i64p), ("idx_B", ctypes.c_char_p),
+                ("beta", ctypes.c_double),
+                ("C", _vp), ("ndim_C", ctypes.c_int), ("lens_C", _i64p), ("strides_C", _i64p), ("idx_C", ctypes.c_char_p)]
 
 
 def lib():
@@ -77,6 +86,7 @@ def lib():
         L.tc_batch_set_tile.argtypes = [_vp, ctypes.c_int]
         L.tc_batch_autotune.argtypes = [_vp, ctypes.c_int, _vp, ctypes.POINTER(ctypes.c_double)]
         L.tc_batch_problem_tile.argtypes = [_vp, ctypes.c_int, ip]
+        L.tc_contract_batched.argtypes = [ctypes.c_int, ctypes.POINTER(_Problem), ctypes.c_int, ctypes.c_int, _vp]
         L.tc_scatter_vector.argtypes = [ctypes.c_int, _i64p, _i64p, _i64p]
         L.tc_block_strides.argtypes = [_i64p, ctypes.c_int64, ctypes.c_int64, _i64p]
         L.tc_permute.argtypes = [_vp, _vp, ctypes.c_int, _i64p, _i64p, _i64p, ctypes.c_int, _vp]
@@ -346,6 +356,27 @@ def contract(A, idx_A, B, idx_B, idx_C, alpha=1.0, beta=0.0, out=None, mode="nat
                              *_desc(tuple(out.shape), out.stride(), idx_C), _dtype_code(A.dtype), mode_code,
                              _stream_ptr(stream)))
     return out
+
+
+def contract_batched(problems, mode="native", stream=None):
+    """One-shot batch: C_i[idx_C] = alpha_i * A_i . B_i + beta_i * C_i for
+    every (A, idx_A, B, idx_B, C, idx_C, alpha, beta) in ``problems`` (torch
+    tensors on the current device, one dtype), in persistent launches.
+    Synchronous (waits for the stream); for repeated use build a ``Batch``."""
+    mode_code = MODES[mode] if isinstance(mode, str) else mode
+    n = len(problems)
+    if n == 0:
+        return
+    dt = problems[0][0].dtype
+    keep, arr = [], (_Problem * n)()
+    for i, (A, ia, B, ib, C, ic, alpha, beta) in enumerate(problems):
+        if A.dtype != dt or B.dtype != dt or C.dtype != dt:
+            raise TypeError("every tensor of a batch must have the same dtype")
+        ds = [_desc(tuple(t.shape), t.stride(), lab) for t, lab in ((A, ia), (B, ib), (C, ic))]
+        keep.append(ds)
+        f = [(nd, ctypes.cast(ln, _i64p), ctypes.cast(st, _i64p), lab) for nd, ln, st, lab in ds]
+        arr[i] = _Problem(float(alpha), _ptr(A), *f[0], _ptr(B), *f[1], float(beta), _ptr(C), *f[2])
+    _check(lib().tc_contract_batched(n, arr, _dtype_code(dt), mode_code, _stream_ptr(stream)))
 
 
 def contract_noalloc(A, idx_A, B, idx_B, idx_C, out, alpha=1.0, beta=0.0, mode="native", stream=None):

@@ -122,3 +122,31 @@ def test_autotune_batch_and_plan():
     plan.close()
     plan2.close()
     batch.close()
+
+
+def test_contract_batched_one_shot(oracle_mod):
+    """tc_contract_batched (one call: plans, batch, run, free) gives, bit for
+    bit, what a batch built with tc_batch_create gives (the same plans and
+    per-problem tile classes), on cfg5 instances, a ragged problem with
+    beta != 0 and one whose operands' unit strides lie on different
+    contracted indices; every output against the oracle."""
+    torch = require_gpu()
+    from paper_1607_00291_amd import tc
+    probs = subset(12) + [inputs.random_problem(7100, 2, 2, 2, lo=3, hi=23, beta=0.5, alpha=-1.5),
+                          inputs.p_conflict_problem(7101, {"e": 13, "g": 3, "f": 10, "i": 150, "j": 70}, beta=0.25)]
+    dev = [(to_dev(p.A), to_dev(p.B), to_dev(p.C)) for p in probs]
+    one = [to_dev(p.C) for p in probs]
+    print(f"case contract_batched {len(probs)} problems", flush=True)
+    tc.contract_batched([(A, p.idx_A, B, p.idx_B, C1, p.idx_C, p.alpha, p.beta)
+                         for p, (A, B, _), C1 in zip(probs, dev, one)])
+    batch = tc.Batch([(A, p.idx_A, B, p.idx_B, C, p.idx_C, p.alpha, p.beta) for p, (A, B, C) in zip(probs, dev)])
+    batch.execute()
+    torch.cuda.synchronize()
+    batch.close()
+    for p, (_, _, C), C1 in zip(probs, dev, one):
+        assert torch.equal(C, C1), p.name
+        ref = np.array(p.C, order="F", copy=True)
+        oracle_mod.contract(p.alpha, p.A, p.idx_A, p.B, p.idx_B, p.beta, ref, p.idx_C)
+        bound = fp64_bound(p.mnk()[2], p.alpha, np.max(np.abs(p.A)), np.max(np.abs(p.B)), p.beta,
+                           np.max(np.abs(p.C)))
+        assert np.max(np.abs(to_host(C1) - ref)) <= bound, p.name

@@ -408,6 +408,21 @@ def test_batch_problem_tile_abi_errors():
     assert L.tc_batch_problem_tile(None, 0, ctypes.byref(t)) == -1
 
 
+def test_contract_batched_abi_errors_and_host_tensors():
+    """tc_contract_batched: argument errors before any device work, and the
+    binding refuses host tensors."""
+    import torch
+    L = tc.lib()
+    assert L.tc_contract_batched(0, None, tc.TC_F64, tc.TC_NATIVE, None) == 0
+    assert L.tc_contract_batched(-1, None, tc.TC_F64, tc.TC_NATIVE, None) == -10  # TC_ERR_ARG
+    assert L.tc_contract_batched(2, None, tc.TC_F64, tc.TC_NATIVE, None) == -1  # TC_ERR_NULL
+    A = torch.zeros(3, 4, dtype=torch.float64)
+    B = torch.zeros(4, 5, dtype=torch.float64)
+    C = torch.zeros(3, 5, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        tc.contract_batched([(A, "ik", B, "kj", C, "ij", 1.0, 0.0)])
+
+
 def test_binding_refuses_host_tensors():
     """A CPU tensor never reaches the library: its host address would be
     meaningless to the kernels."""
