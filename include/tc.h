@@ -263,7 +263,8 @@ typedef struct tc_problem {
  * and it allocates and uploads the batch tables on every call: for repeated
  * batches or graph capture, build a batch once with tc_batch_create and
  * replay tc_batch_execute.  count = 0 does nothing; TC_ERR_NULL for a NULL
- * problem array with count > 0, TC_ERR_ARG for count < 0; otherwise the
+ * problem array with count > 0, TC_ERR_ARG for count < 0 or a stream under
+ * graph capture; otherwise the
  * checks and errors of tc_contract and tc_batch_create (mixed dtypes cannot
  * occur: dtype and mode apply to every problem). */
 int tc_contract_batched(int count, const tc_problem* problems, int dtype, int mode, void* stream);

@@ -995,6 +995,10 @@ int tc_contract_batched(int count, const tc_problem* probs, int dtype, int mode,
             set_error("problems is NULL");
             return TC_ERR_NULL;
         }
+        if (capturing((hipStream_t)stream)) {
+            set_error("tc_contract_batched is synchronous and cannot be captured: capture tc_batch_execute instead");
+            return TC_ERR_ARG;
+        }
         std::vector<const tc_plan*> plans((size_t)count);
         std::vector<double> alpha((size_t)count), beta((size_t)count);
         std::vector<const void*> A((size_t)count), B((size_t)count);
