@@ -183,6 +183,16 @@ __device__ __forceinline__ int64_t uniform(int64_t x) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Calls f(std::integral_constant<int, I>()) for I = 0 .. N-1 in order.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>()), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>());
+}
+
 // XCD-aware tile order.  Workgroups are dispatched round-robin over the 8
 // XCDs (workgroup w runs on XCD w % 8), each with its own L2.  Workgroup w is
 // given tile g = (w % 8) * T/8 + w / 8 of a grouped enumeration that walks
@@ -230,7 +240,7 @@ __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint3
 // written to a k-major LDS stage.  Element e = t + NTHR * i of a stage is
 // (row, kk) with the row index fastest when the operand's lanes run along its
 // free index (LR), and kk fastest when they run along k.
-template <typename T, typename OffT, int R, int KT, int NTHR, bool LR>
+template <typename T, typename OffT, int R, int KT, int NTHR, bool LR, int SLOTS = 1>
 struct PackOp {
     static constexpr int E = R * KT / NTHR;
     static constexpr int LD = Pitch<R, LR>::value;
@@ -240,8 +250,8 @@ struct PackOp {
     static __device__ __forceinline__ int ridx(int e) { return LR ? e % R : e / KT; }
     static __device__ __forceinline__ int kidx(int e) { return LR ? e / R : e % KT; }
 
-    OffT o[E];  // offsets of this thread's rows, fixed per tile; -1 past the edge
-    T r[E];     // one stage in flight
+    OffT o[E];       // offsets of this thread's rows, fixed per tile; -1 past the edge
+    T r[SLOTS][E];  // stages in flight
 
     __device__ __forceinline__ void init(const OffT* rowvec, OffT r0, OffT rmax, int t) {
 #pragma unroll
@@ -255,8 +265,9 @@ struct PackOp {
     // Global gather of k block kb.  A valid block stride (Sec. 6.2) replaces
     // the per-element scatter-vector reads along k; the choice is uniform.
     // REG = 1: every block of this operand is known to have one (no per-k
-    // offset reads compiled in); REG = -1: decided per block.
-    template <int REG = -1>
+    // offset reads compiled in); REG = -1: decided per block.  SL: the
+    // register slot that receives the stage.
+    template <int REG = -1, int SL = 0>
     __device__ __forceinline__ void load(const T* base, int64_t span, const OffT* kvec, const OffT* kbs, OffT kb, OffT K,
                                          int t) {
         const OffT k0 = kb * KT;
@@ -290,32 +301,33 @@ struct PackOp {
             for (int i = 0; i < E; ++i) {
                 const bool ok = o[i] >= 0 && k0 + kidx(t + NTHR * i) < K;
                 const uint32_t vo = ok ? (uint32_t)(o[i] + ko[i]) * (uint32_t)sizeof(T) : kOutOfRange;
-                r[i] = buf_load<T>(rs, vo, soff);
+                r[SL][i] = buf_load<T>(rs, vo, soff);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < E; ++i) {
                 const bool ok = o[i] >= 0 && k0 + kidx(t + NTHR * i) < K;
                 const T x = base[ok ? kbase + o[i] + ko[i] : OffT(0)];
-                r[i] = ok ? x : T(0);
+                r[SL][i] = ok ? x : T(0);
             }
         }
     }
 
+    template <int SL = 0>
     __device__ __forceinline__ void store(T* stage, int t) const {
 #pragma unroll
         for (int i = 0; i < E; ++i) {
             const int e = t + NTHR * i;
-            stage[kidx(e) * LD + ridx(e)] = r[i];
+            stage[kidx(e) * LD + ridx(e)] = r[SL][i];
         }
     }
 };
 
 // Both operands of a tile, every thread gathering its share of each.
-template <typename T, typename OffT, int MT, int NT, int KT, int NTHR, bool XM, bool YN>
+template <typename T, typename OffT, int MT, int NT, int KT, int NTHR, bool XM, bool YN, int SLOTS = 1>
 struct Pack {
-    typedef PackOp<T, OffT, MT, KT, NTHR, XM> PX;
-    typedef PackOp<T, OffT, NT, KT, NTHR, YN> PY;
+    typedef PackOp<T, OffT, MT, KT, NTHR, XM, SLOTS> PX;
+    typedef PackOp<T, OffT, NT, KT, NTHR, YN, SLOTS> PY;
     static constexpr int LDX = PX::LD, LDY = PY::LD, XS = PX::S, YS = PY::S;
     static constexpr int ELEMS = 2 * (XS + YS);  // [X0][X1][Y0][Y1]
     PX px;
@@ -324,14 +336,15 @@ struct Pack {
         px.init(a.rX, m0, a.m, t);
         py.init(a.cY, n0, a.n, t);
     }
-    template <int REG = -1>
+    template <int REG = -1, int SL = 0>
     __device__ __forceinline__ void load(const KArgs<T, OffT>& a, OffT kb, int t) {
-        px.template load<REG>(a.X, a.spanX, a.cX, a.kbsX, kb, a.k, t);
-        py.template load<REG>(a.Y, a.spanY, a.rY, a.kbsY, kb, a.k, t);
+        px.template load<REG, SL>(a.X, a.spanX, a.cX, a.kbsX, kb, a.k, t);
+        py.template load<REG, SL>(a.Y, a.spanY, a.rY, a.kbsY, kb, a.k, t);
     }
+    template <int SL = 0>
     __device__ __forceinline__ void store(T* smem, int buf, int t) const {
-        px.store(smem + buf * XS, t);
-        py.store(smem + 2 * XS + buf * YS, t);
+        px.template store<SL>(smem + buf * XS, t);
+        py.template store<SL>(smem + 2 * XS + buf * YS, t);
     }
 };
 
@@ -429,7 +442,15 @@ struct TileRegular {
     static constexpr int FM = WTM / 16, FN = WTN / 16;
     static_assert(KT % 4 == 0, "KT must be a multiple of the MFMA depth");
     static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tiles are made of 16x16 fragments");
-    typedef Pack<T, OffT, MT, NT, KT, NTHR, XM, YN> P;
+    // gathered stages in flight per thread: one, except on the 32 x 32 tile
+    // of four one-fragment waves, whose stages are short against a
+    // gather's latency (a few, within the 63 loads the memory counter tracks)
+    static constexpr int LOADS = (MT + NT) * KT / NTHR;
+    static constexpr int SLOTS = !(MT == 32 && NT == 32 && WM * WN == 4) ? 1
+                                 : 4 * LOADS <= 63                       ? 4
+                                 : 3 * LOADS <= 63                       ? 3
+                                                                         : 1;
+    typedef Pack<T, OffT, MT, NT, KT, NTHR, XM, YN, SLOTS> P;
     static constexpr int SMEM = P::ELEMS;
 
     static __device__ __forceinline__ void run(const KArgs<T, OffT>& a, int64_t tile, T* smem) {
@@ -452,35 +473,61 @@ struct TileRegular {
                 for (int r = 0; r < 4; ++r) acc[i][j][r] = T(0);
 
         const OffT nkb = (a.k + KT - 1) / KT;
+        auto compute = [&](int buf) {
+            const T* bx = smem + buf * P::XS + wm * WTM;
+            const T* by = smem + 2 * P::XS + buf * P::YS + wn * WTN;
+#pragma unroll
+            for (int s = 0; s < KT / 4; ++s) {
+                const int kr = 4 * s + (lane >> 4);
+                typename M::afrag fa[FM];
+                typename M::bfrag fb[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) fa[i] = M::load_a(bx + kr * P::LDX + 16 * i, lane);
+#pragma unroll
+                for (int j = 0; j < FN; ++j) fb[j] = M::load_b(by + kr * P::LDY + 16 * j, lane);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) M::run(fa[i], fb[j], acc[i][j]);
+            }
+        };
         // The gathers of stage kb + 1 and their LDS store run with no branch
         // around them: past the last stage they re-read the last block and
         // fill the LDS buffer that no stage reads any more.
         auto pipeline = [&](auto reg) {
             constexpr int RG = decltype(reg)::value;
-            pk.template load<RG>(a, 0, tid);
-            pk.store(smem, 0, tid);
-            __syncthreads();
-            for (OffT kb = 0; kb < nkb; ++kb) {
-                const int buf = (int)(kb & 1);
-                pk.template load<RG>(a, kb + 1 < nkb ? kb + 1 : kb, tid);
-                const T* bx = smem + buf * P::XS + wm * WTM;
-                const T* by = smem + 2 * P::XS + buf * P::YS + wn * WTN;
-#pragma unroll
-                for (int s = 0; s < KT / 4; ++s) {
-                    const int kr = 4 * s + (lane >> 4);
-                    typename M::afrag fa[FM];
-                    typename M::bfrag fb[FN];
-#pragma unroll
-                    for (int i = 0; i < FM; ++i) fa[i] = M::load_a(bx + kr * P::LDX + 16 * i, lane);
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) fb[j] = M::load_b(by + kr * P::LDY + 16 * j, lane);
-#pragma unroll
-                    for (int i = 0; i < FM; ++i)
-#pragma unroll
-                        for (int j = 0; j < FN; ++j) M::run(fa[i], fb[j], acc[i][j]);
-                }
-                pk.store(smem, buf ^ 1, tid);
+            if constexpr (SLOTS == 1) {
+                pk.template load<RG>(a, 0, tid);
+                pk.store(smem, 0, tid);
                 __syncthreads();
+                for (OffT kb = 0; kb < nkb; ++kb) {
+                    const int buf = (int)(kb & 1);
+                    pk.template load<RG>(a, kb + 1 < nkb ? kb + 1 : kb, tid);
+                    compute(buf);
+                    pk.store(smem, buf ^ 1, tid);
+                    __syncthreads();
+                }
+            } else {
+                // stages kb + 1 .. kb + SLOTS in flight in registers while
+                // stage kb is computed from LDS
+                static_for<SLOTS>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    pk.template load<RG, i>(a, nkb > i ? (OffT)i : nkb - 1, tid);
+                });
+                pk.template store<0>(smem, 0, tid);
+                __syncthreads();
+                for (OffT kb0 = 0; kb0 < nkb; kb0 += SLOTS)
+                    static_for<SLOTS>([&](auto ic) {
+                        constexpr int i = decltype(ic)::value;
+                        const OffT kb = kb0 + i;
+                        const int buf = (int)(kb & 1);
+                        // slot i held stage kb, already in LDS: refill it
+                        pk.template load<RG, i>(a, kb + SLOTS < nkb ? kb + SLOTS : nkb - 1, tid);
+                        if (kb < nkb) compute(buf);
+                        // stage kb + 1, gathered SLOTS - 1 stages ago
+                        pk.template store<(i + 1) % SLOTS>(smem, buf ^ 1, tid);
+                        __syncthreads();
+                    });
             }
         };
         if (nkb > 0) {
@@ -495,16 +542,6 @@ struct TileRegular {
 // The pack stage of one operand, with the operand (and so the lane
 // direction and LDS pitch) chosen at run time: used where a wave gathers
 // either X or Y, so that only one set of gather registers is live.
-// Calls f(std::integral_constant<int, I>()) for I = 0 .. N-1 in order.
-template <typename F, int... I>
-__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
-    (f(std::integral_constant<int, I>()), ...);
-}
-template <int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-    static_for_impl(f, std::make_integer_sequence<int, N>());
-}
-
 template <typename T, typename OffT, int R, int KT, int NTHR, int SLOTS = 1>
 struct PackRole {
     static constexpr int E = R * KT / NTHR;

@@ -421,7 +421,10 @@ int choose_tile(const Plan& p, bool batched) {
     const TileCfg* tab = tile_table(p.dtype, p.mode);
     const TileRate* rate = rate_table(p.dtype, p.mode);
     const int nt = tile_count(p.dtype, p.mode);
-    const double cus = 256.0, cache_bw = 4e12, hbm_bw = 5e12;
+    // operands stream from the caches at about 8 TB/s in a single
+    // contraction; in a batch the caches hold many problems' panels at once,
+    // and 4 TB/s fits the batches measured
+    const double cus = 256.0, cache_bw = batched ? 4e12 : 8e12, hbm_bw = 5e12;
     const double esize = p.dtype == TC_F64 ? 8.0 : 4.0;
     const double k = (double)std::max<int64_t>(p.k, 1);
     int best = 0;
@@ -432,6 +435,10 @@ int choose_tile(const Plan& p, bool batched) {
         // holds all four lane variants of the tile; for the pinwheels that
         // kernel spills registers, so by default batches use the other layouts
         if (batched && (t.layout == 1 || t.layout == 2)) continue;
+        // the 32 x 32 tiles win single small launches by parallelism, which a
+        // batch supplies from its other problems; inside batches they ran
+        // slower than the larger tiles
+        if (batched && t.MT * t.NT <= 32 * 32) continue;
         const double tiles = (double)((p.m + t.MT - 1) / t.MT) * (double)((p.n + t.NT - 1) / t.NT);
         // a batch keeps every CU at the tile's full residency with the tiles
         // of all its problems, so a problem's share is its padded work at that

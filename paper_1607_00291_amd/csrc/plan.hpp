@@ -88,7 +88,8 @@ void set_plan_tile(Plan* p, int tile);
 // Pick a tile configuration from the shape (wave-quantisation aware model).
 // Tile configuration of least estimated time; batched skips the pinwheel
 // layouts (a batched launch does not run the all-compute one, and the
-// specialised-wave one spills registers inside the batched kernel).
+// specialised-wave one spills registers inside the batched kernel) and the
+// 32 x 32 tiles.
 int choose_tile(const Plan& p, bool batched = false);
 // Shape signature used by the autotuner cache.
 std::string plan_signature(const Plan& p);
