@@ -511,7 +511,10 @@ def sweep(tc, inputs, steps, warmup, square=(512, 1024, 2048, 4096), rankk=(8, 3
 def batched(tc, inputs, steps, warmup):
     """512 contractions (extents 4..64, random permutations) as one batch
     (persistent launches, one per tile class, or one class for all if the
-    autotuner finds that faster) against 512 sequential plan launches."""
+    autotuner finds that faster) against 512 sequential plan launches.  Also
+    reports the default mode (every problem in the class the planner picks for
+    it): its total time and, per tile class, the problems, flop share and the
+    time of that class's launch timed alone."""
     import torch
     probs, tensors, total = [], [], 0.0
     for i in range(512):
@@ -520,9 +523,26 @@ def batched(tc, inputs, steps, warmup):
         probs.append(p)
         tensors.append((A, B, C))
         total += p.flops()
-    batch = tc.Batch([(A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 0.0) for p, (A, B, C) in zip(probs, tensors)])
+    items = [(A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 0.0) for p, (A, B, C) in zip(probs, tensors)]
+    batch = tc.Batch(items)
+    reps = max(steps // 5, 3)
+    ms_pc = time_calls(batch.execute, reps, 1)
+    classes = {}
+    for i in range(len(probs)):
+        t = batch.problem_tile(i)
+        if t >= 0:
+            classes.setdefault(t, []).append(i)
+    per_class = {}
+    for t, idx in sorted(classes.items()):
+        sub = tc.Batch([items[i] for i in idx])
+        sub.tile = t
+        ms = time_calls(sub.execute, reps, 1)
+        fl = sum(probs[i].flops() for i in idx)
+        per_class[str(t)] = {"problems": len(idx), "flop_share": round(fl / total, 4), "ms": round(ms, 3),
+                             "gflops": round(fl / ms / 1e6, 1)}
+        sub.close()
     tile, _ = batch.autotune(reps=2)
-    ms_b = time_calls(batch.execute, max(steps // 5, 3), 1)
+    ms_b = time_calls(batch.execute, reps, 1)
     plans = [plan_runner(tc, A, p.idx_A, B, p.idx_B, C, p.idx_C, 1.0, 0.0) for p, (A, B, C) in zip(probs, tensors)]
 
     def seq():
@@ -540,7 +560,9 @@ def batched(tc, inputs, steps, warmup):
             "batched_gflops": round(total / ms_b / 1e6, 1),
             "batched_frac_of_fp64_peak": round(total / ms_b / 1e9 / PEAK_FP64_TFLOPS, 4),
             "sequential_gflops": round(total / ms_s / 1e6, 1), "batch_tile": tile,
-            "work_items": info["work_items"], "grid": info["grid"]}
+            "work_items": info["work_items"], "grid": info["grid"],
+            "default_per_class": {"ms": round(ms_pc, 3), "gflops": round(total / ms_pc / 1e6, 1),
+                                  "classes": per_class}}
 
 
 def main():
