@@ -30,6 +30,7 @@ struct tc_batch {
     std::vector<tc::BatchItemDev> host;  // per problem that launches work (device pointers filled)
     std::vector<int> host_of;            // per problem: its index in `host`, -1 for an empty problem
     std::vector<int> best;               // per problem: its own regular tile class
+    std::vector<double> slow;            // per problem: time per flop relative to one whose k blocks all have a stride
     std::vector<int> order;              // problem index of each table entry
     struct Segment {
         int tile, first, count, grid;
@@ -627,8 +628,8 @@ namespace tc {
 // Work-item counts of a batch, the table upload and the workgroups' work
 // lists.  The table is grouped by tile class (one persistent launch per class,
 // the class with the most work first); inside a class problems are ordered by
-// decreasing k (the cost of one tile), the order in which the work lists
-// below hand out their tiles.
+// decreasing cost of one tile (k times the problem's relative time per flop),
+// the order in which the work lists below hand out their tiles.
 static int batch_layout(tc_batch* b) {
     const TileCfg* tab = tile_table(b->dtype, b->mode);
     const std::vector<BatchItemDev>& items = b->host;
@@ -651,8 +652,11 @@ static int batch_layout(tc_batch* b) {
     for (size_t i = 0; i < n; ++i) idx[i] = (int)i;
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
         if (cls[x] != cls[y]) return pos[cls[x]] < pos[cls[y]];
-        return items[x].k > items[y].k;
+        return (double)items[x].k * b->slow[(size_t)x] > (double)items[y].k * b->slow[(size_t)y];
     });
+    std::vector<double> slow_of;  // per table entry
+    slow_of.reserve(n);
+    for (size_t e = 0; e < n; ++e) slow_of.push_back(b->slow[(size_t)idx[e]]);
     std::vector<BatchItemDev> table;
     table.reserve(n);
     b->segs.clear();
@@ -698,12 +702,13 @@ static int batch_layout(tc_batch* b) {
         b->grid = std::max(b->grid, sg.grid);
     }
     // Work lists: within each launch, the (problem, tile) work items in
-    // decreasing cost (the table is in decreasing k inside a class; every tile
+    // decreasing cost (the table is in that order inside a class; every tile
     // of a problem costs the same), each given to the workgroup with the least
     // work so far, ties to the lower index (longest processing time first).
     // The lists are fixed here, so a launch needs no counter and no reset
     // between graph replays, and the assignment is deterministic.  Cost of a
-    // tile: its k plus three stages for the prologue and the C update.
+    // tile: its k plus three stages for the prologue and the C update, times
+    // the problem's relative time per flop.
     std::vector<int32_t> host;
     for (auto& sg : b->segs) {
         const TileCfg& t = tab[sg.tile];
@@ -719,7 +724,7 @@ static int batch_layout(tc_batch* b) {
                 set_error("a batch problem has more than 2^31 tiles");
                 return TC_ERR_ARG;
             }
-            const double cost = (double)std::max<int64_t>(it.k, 1) + 3.0 * t.KT;
+            const double cost = ((double)std::max<int64_t>(it.k, 1) + 3.0 * t.KT) * slow_of[(size_t)(sg.first + e)];
             for (int64_t w = 0; w < tiles; ++w) {
                 Load l = heap.top();
                 heap.pop();
@@ -949,6 +954,9 @@ static int batch_create(tc_batch** out, int count, const tc_plan* const* plans, 
         b->host_of[i] = (int)b->host.size();
         b->host.push_back(it);
         b->best.push_back(choose_tile(p, true));  // layouts a batch runs
+        // measured in batches: a sub-blocked k order runs at about half the
+        // rate, k blocks without a block stride at about 0.8 of it
+        b->slow.push_back(p.sub_a >= 0 ? 2.0 : (it.kregX && it.kregY) ? 1.0 : 1.25);
     }
     if (total) {
         hipError_t e = hipMemcpy(b->vectors, host.data(), total * w, hipMemcpyHostToDevice);
