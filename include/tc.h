@@ -37,7 +37,17 @@
  *     mode: TC_NATIVE (multiply-add in the storage type; FP64 accumulates in
  *     FP64, FP32 in FP32) or TC_SPLIT_BF16X3 (TC_F32 only: each operand is
  *     split into bf16 hi + lo, three products hi*hi + hi*lo + lo*hi on bf16
- *     matrix cores, FP32 accumulation).
+ *     matrix cores, FP32 accumulation).  One split tile configuration (the
+ *     "packed split tile", reported with "layout": 4 by tc_plan_describe)
+ *     first splits each operand once into hi/lo panels in a device workspace
+ *     of (ceil(m/144) + ceil(n/144)) * ceil(k/32) * 18432 bytes, which the
+ *     plan owns ("workspace_bytes"): one per (device, stream) the plan runs
+ *     on, allocated by the first call on that stream outside graph capture
+ *     (TC_ERR_CAPTURE under capture without it; TC_ERR_NOMEM if it cannot be
+ *     allocated), freed by tc_plan_destroy.  Calls on one stream are ordered
+ *     by the stream; calls on different streams use different workspaces.
+ *     A graph captured on a stream uses that stream's workspace, so its
+ *     replays must not overlap eager calls of the plan on that stream.
  *   - stream is a hipStream_t (NULL = the null stream).  Calls are
  *     asynchronous on it; device faults surface at the caller's next
  *     synchronisation.  The results of one plan and one tile configuration
@@ -109,7 +119,9 @@ int tc_contract(double alpha,
  * Every call on a GPU reuses that GPU's array and it keeps the last call's
  * contents: calls that may overlap in time on one GPU (other streams, other
  * threads) race and must be serialised by the caller; calls on one stream
- * are ordered.
+ * are ordered.  Where tc_contract would run the packed split tile, which
+ * needs a workspace, this entry point runs the split tile of the same sizes
+ * that splits in its own producer waves (the same bits, slower).
  */
 #define TC_NOALLOC_SCRATCH_BYTES (8u << 20)
 int tc_contract_noalloc(double alpha,
@@ -143,8 +155,11 @@ int tc_plan_upload(tc_plan* plan);
 
 /* Execute a plan on device data (Sec. 6.2 BSMTC as one kernel launch: gather
  * of A and B slivers into LDS through the offset vectors, matrix-core
- * micro-kernel, alpha/beta scatter-store of C tiles).  Safe to record into a
- * hipGraph once the plan has been uploaded to the capturing device. */
+ * micro-kernel, alpha/beta scatter-store of C tiles; the packed split tile
+ * adds a split-and-pack launch before it, Sec. 6.1's packing done once for
+ * the whole operand).  Safe to record into a hipGraph once the plan has been
+ * uploaded to the capturing device (and, for the packed split tile, has run
+ * once on the capturing stream). */
 int tc_plan_execute(const tc_plan* plan, double alpha, const void* A, const void* B, double beta, void* C,
                     void* stream);
 

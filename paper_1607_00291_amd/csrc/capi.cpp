@@ -144,6 +144,11 @@ static void free_device(Plan* p) {
             d.buf = nullptr;
             d.bytes = 0;
         }
+    for (auto& per_dev : p->ws) {
+        for (auto& w : per_dev)
+            if (w.second.first) hipFree(w.second.first);
+        per_dev.clear();
+    }
 }
 
 static bool overlaps(const void* a, int64_t na, const void* b, int64_t nb, size_t w) {
@@ -230,6 +235,50 @@ static int check_call(const Plan& p, double alpha, const void* A, const void* B,
     return TC_OK;
 }
 
+// Workspace of the packed split tile for a launch on `stream` (null for every
+// other tile): the plan keeps one buffer per (device, stream) it ran on, so
+// that calls on different streams never share one, while calls on one stream
+// are ordered by the stream.  Allocated (or grown, after the stream's earlier
+// work has finished) outside capture; under capture it must already exist.
+static int plan_workspace(const Plan& p, hipStream_t stream, void** ws) {
+    *ws = nullptr;
+    const TileCfg& t = tile_table(p.dtype, p.mode)[p.tile];
+    if (p.mode != TC_SPLIT_BF16X3 || t.layout != 4 || p.k_empty || p.k == 0) return TC_OK;
+    const size_t need = (size_t)split_pack_bytes(t, p.m, p.n, p.k);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hipfail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device index beyond the library's limit of 16");
+        return TC_ERR_ARG;
+    }
+    std::lock_guard<std::mutex> g(p.dev_mu);
+    std::pair<void*, size_t>& w = p.ws[dev][(void*)stream];
+    if (w.first && w.second >= need) {
+        *ws = w.first;
+        return TC_OK;
+    }
+    if (capturing(stream)) {
+        set_error("the packed split tile's workspace for this stream is made by a first call outside capture");
+        return TC_ERR_CAPTURE;
+    }
+    if (w.first) {
+        e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hipfail(e, "hipStreamSynchronize before growing the split panels");
+        hipFree(w.first);
+        w = {nullptr, 0};
+    }
+    e = hipMalloc(&w.first, need);
+    if (e != hipSuccess) {
+        w = {nullptr, 0};
+        set_error("hipMalloc of the split panels (" + std::to_string(need) + " bytes) failed");
+        return TC_ERR_NOMEM;
+    }
+    w.second = need;
+    *ws = w.first;
+    return TC_OK;
+}
+
 static int execute(const tc_plan* plan, double alpha, const void* A, const void* B, double beta, void* C,
                    hipStream_t stream) {
     const Plan& p = *plan->p;
@@ -248,7 +297,9 @@ static int execute(const tc_plan* plan, double alpha, const void* A, const void*
     } else if ((st = ensure_uploaded(p, &dv))) {
         return st;
     }
-    return launch_plan(p, *dv, alpha, A, B, beta, C, stream);
+    void* ws = nullptr;
+    if (alpha != 0.0 && (st = plan_workspace(p, stream, &ws))) return st;
+    return launch_plan(p, *dv, alpha, A, B, beta, C, stream, ws);
 }
 
 static int create(tc_plan** out, int ndim_A, const int64_t* lens_A, const int64_t* strides_A, const char* idx_A,
@@ -611,7 +662,8 @@ int tc_contract_noalloc(double alpha, const void* A, int ndim_A, const int64_t* 
         bool run = false;
         if ((st = check_call(p, alpha, A, B, C, (hipStream_t)stream, &run)) || !run) return st;
         if ((st = noalloc_vectors(p, (hipStream_t)stream, &dv))) return st;
-        return launch_plan(p, dv, alpha, A, B, beta, C, (hipStream_t)stream);
+        // no workspace: a packed split tile runs as its in-kernel-split twin
+        return launch_plan(p, dv, alpha, A, B, beta, C, (hipStream_t)stream, nullptr);
     } catch (const std::bad_alloc&) {
         set_error("out of host memory");
         return TC_ERR_NOMEM;

@@ -5,8 +5,8 @@
 namespace tc {
 
 int launch_typed_f32_i32(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
-                       void* C, hipStream_t s) {
-    return launch_typed<float, int32_t>(p, dv, alpha, A, B, beta, C, s);
+                       void* C, hipStream_t s, void* ws) {
+    return launch_typed<float, int32_t>(p, dv, alpha, A, B, beta, C, s, ws);
 }
 
 int batch_dispatch_f32_i32(int dtype, int tile, bool launch, const BatchItemDev* items, const int32_t* off,

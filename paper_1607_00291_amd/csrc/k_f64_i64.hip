@@ -5,8 +5,8 @@
 namespace tc {
 
 int launch_typed_f64_i64(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
-                       void* C, hipStream_t s) {
-    return launch_typed<double, int64_t>(p, dv, alpha, A, B, beta, C, s);
+                       void* C, hipStream_t s, void* ws) {
+    return launch_typed<double, int64_t>(p, dv, alpha, A, B, beta, C, s, ws);
 }
 
 int batch_dispatch_f64_i64(int dtype, int tile, bool launch, const BatchItemDev* items, const int32_t* off,

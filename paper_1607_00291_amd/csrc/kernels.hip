@@ -10,33 +10,33 @@
 namespace tc {
 
 int launch_typed_f64_i32(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
-                       void* C, hipStream_t s);
+                       void* C, hipStream_t s, void* ws);
 int batch_dispatch_f64_i32(int dtype, int tile, bool launch, const BatchItemDev* items, const int32_t* off,
                          const int32_t* ent, int64_t total, int grid, hipStream_t s);
 int launch_typed_f64_i64(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
-                       void* C, hipStream_t s);
+                       void* C, hipStream_t s, void* ws);
 int batch_dispatch_f64_i64(int dtype, int tile, bool launch, const BatchItemDev* items, const int32_t* off,
                          const int32_t* ent, int64_t total, int grid, hipStream_t s);
 int launch_typed_f32_i32(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
-                       void* C, hipStream_t s);
+                       void* C, hipStream_t s, void* ws);
 int batch_dispatch_f32_i32(int dtype, int tile, bool launch, const BatchItemDev* items, const int32_t* off,
                          const int32_t* ent, int64_t total, int grid, hipStream_t s);
 int launch_typed_f32_i64(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
-                       void* C, hipStream_t s);
+                       void* C, hipStream_t s, void* ws);
 int batch_dispatch_f32_i64(int dtype, int tile, bool launch, const BatchItemDev* items, const int32_t* off,
                          const int32_t* ent, int64_t total, int grid, hipStream_t s);
 
 int launch_plan(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
-                void* C, hipStream_t s) {
+                void* C, hipStream_t s, void* ws) {
     if (p.mode != TC_NATIVE && !(p.mode == TC_SPLIT_BF16X3 && p.dtype == TC_F32)) {
         set_error("split-bf16 mode needs FP32 storage");
         return TC_ERR_DTYPE;
     }
     if (p.dtype == TC_F64)
-        return p.off64 ? launch_typed_f64_i64(p, dv, alpha, A, B, beta, C, s)
-                       : launch_typed_f64_i32(p, dv, alpha, A, B, beta, C, s);
-    return p.off64 ? launch_typed_f32_i64(p, dv, alpha, A, B, beta, C, s)
-                   : launch_typed_f32_i32(p, dv, alpha, A, B, beta, C, s);
+        return p.off64 ? launch_typed_f64_i64(p, dv, alpha, A, B, beta, C, s, ws)
+                       : launch_typed_f64_i32(p, dv, alpha, A, B, beta, C, s, ws);
+    return p.off64 ? launch_typed_f32_i64(p, dv, alpha, A, B, beta, C, s, ws)
+                   : launch_typed_f32_i32(p, dv, alpha, A, B, beta, C, s, ws);
 }
 
 int launch_batch(int dtype, int mode, int tile, bool off64, const BatchItemDev* items, const int32_t* off,

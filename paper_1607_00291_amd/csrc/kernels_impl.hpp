@@ -163,6 +163,7 @@ struct KArgs {
     int kregX, kregY;  // 1: every k block of X (Y) has a nonzero block stride
     OffT ksX, ksY;     // the block stride shared by every k block of X (Y), else 0
     int xm, yn;        // X gathered with lanes along m (else k), Y along n (else k)
+    const void* packed;  // split panels of X then Y (the packed split tile), else unused
 };
 
 // LDS row pitch (in elements) of a k-major stage: one element of padding when
@@ -1145,13 +1146,31 @@ struct PackQuad {
 // one of the three products of the centre fragment.  This keeps the split's
 // vector work off the compute waves and gives every SIMD the same matrix work
 // (the 3 x 3 wave grid puts three waves on one SIMD).
-template <typename OffT, int KT, bool XM, bool YN>
+//
+// PACKED: the operands were split once beforehand (split_pack_kernel) into
+// panels laid out as the LDS stages hold them, so the producer waves only
+// copy each stage's two panels with 16-byte loads; the compute side is the
+// same, and so are the results, bit for bit.
+template <typename OffT, int KT, bool XM, bool YN, bool PACKED = false>
 struct TileSplitWS {
     static constexpr int MT = 144, NT = 144, NTHR = 512;
     static_assert(KT % 32 == 0, "KT must be a multiple of the bf16 matrix-core depth");
     static constexpr int KTP = KT + 8;  // plane pitch in bf16 (16-byte multiple)
     static constexpr int SLOTS = 2;     // gathered stages in flight per producer thread
     typedef PackQuad<OffT, 144, KT, 128, KTP, SLOTS> PQ;
+    // a packed panel (one operand's 144 rows x KT of one k block): its hi
+    // plane then its lo plane, rows of KT bf16, as CH 16-byte chunks; chunk
+    // c is plane c / (144 CPR), row (c mod 144 CPR) / CPR, k-chunk c mod CPR
+    static constexpr int CPR = KT / 8;
+    static constexpr int CH = 2 * 144 * CPR;
+    static constexpr int CPT = CH / 128;  // chunks per producer thread
+    static_assert(CH % 128 == 0, "a panel splits evenly over two producer waves");
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    // LDS position (in bf16) of chunk c inside one operand's two planes
+    static __device__ __forceinline__ int chunk_lds(int c) {
+        const int pl = c / (144 * CPR), rem = c % (144 * CPR);
+        return pl * PQ::PLANE + (rem / CPR) * KTP + 8 * (rem % CPR);
+    }
     static constexpr int PLANE = PQ::PLANE;
     static constexpr int STAGE = 4 * PLANE;  // X hi, X lo, Y hi, Y lo (bf16 elements)
     static constexpr int SMEM = STAGE > 3 * 256 ? STAGE : 3 * 256;  // two stages, in floats
@@ -1179,20 +1198,48 @@ struct TileSplitWS {
             const OffT* gk = gx ? a.cX : a.rY;
             const OffT* gbs = gx ? a.kbsX : a.kbsY;
             PQ pk;
-            if (gx) pk.init(a.rX, m0, a.m, tt, XM);
-            else pk.init(a.cY, n0, a.n, tt, YN);
+            if constexpr (!PACKED) {
+                if (gx) pk.init(a.rX, m0, a.m, tt, XM);
+                else pk.init(a.cY, n0, a.n, tt, YN);
+            }
             f32x4 accc = {0.f, 0.f, 0.f, 0.f};
             OffT pre_sk = 0, pre_k = 0;
             auto fetch = [&](OffT kb) {
-                pre_sk = uniform(gbs[kb]);
-                pre_k = uniform(gk[kb * KT]);
+                if constexpr (!PACKED) {
+                    pre_sk = uniform(gbs[kb]);
+                    pre_k = uniform(gk[kb * KT]);
+                }
+            };
+            // packed: this operand's panels of the tile's row (column) panel
+            u32x4 cv[PACKED ? SLOTS : 1][PACKED ? CPT : 1];
+            const u32x4* panels =
+                PACKED ? (const u32x4*)a.packed + (gx ? tm : a.tiles_m + tn) * (int64_t)nkb * CH + tt : nullptr;
+            auto load = [&](auto slot, auto reg, OffT kb) {
+                constexpr int SL = decltype(slot)::value;
+                constexpr int RG = decltype(reg)::value;
+                if constexpr (PACKED) {
+                    const u32x4* src = panels + (int64_t)kb * CH;
+#pragma unroll
+                    for (int i = 0; i < CPT; ++i) cv[SL][i] = src[128 * i];
+                } else {
+                    pk.template load_with<SL, RG>(pre_sk, pre_k, gbase, gspan, gk, kb, a.k, tt);
+                }
+            };
+            auto store = [&](auto slot, __bf16* planes) {
+                constexpr int SL = decltype(slot)::value;
+                if constexpr (PACKED) {
+#pragma unroll
+                    for (int i = 0; i < CPT; ++i) *(u32x4*)(planes + chunk_lds(128 * i + tt)) = cv[SL][i];
+                } else {
+                    pk.template store<SL>((uint32_t*)planes, tt);
+                }
             };
             auto body = [&](OffT kb, auto slot, auto reg) {
                 constexpr int SL = decltype(slot)::value;
                 constexpr int RG = decltype(reg)::value;
                 const int buf = (int)(kb & 1);
                 const OffT lk = kb + SLOTS < nkb ? kb + SLOTS : nkb - 1;
-                pk.template load_with<SL, RG>(pre_sk, pre_k, gbase, gspan, gk, lk, a.k, tt);
+                load(slot, reg, lk);
                 fetch(kb + SLOTS + 1 < nkb ? kb + SLOTS + 1 : nkb - 1);
                 if (kb < nkb && wave < 7) {
                     // one of the centre fragment's three products: wave 4
@@ -1206,24 +1253,23 @@ struct TileSplitWS {
                         accc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ca, cb, accc, 0, 0, 0);
                     }
                 }
-                pk.template store<(SL + 1) % SLOTS>((uint32_t*)(gx ? xplane(buf ^ 1) : yplane(buf ^ 1)), tt);
+                store(std::integral_constant<int, (SL + 1) % SLOTS>(), gx ? xplane(buf ^ 1) : yplane(buf ^ 1));
                 __syncthreads();
             };
             auto pipeline = [&](auto reg) {
-                constexpr int RG = decltype(reg)::value;
                 static_for<SLOTS>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
                     fetch(nkb > i ? i : nkb - 1);
-                    pk.template load_with<i, RG>(pre_sk, pre_k, gbase, gspan, gk, nkb > i ? i : nkb - 1, a.k, tt);
+                    load(ic, reg, nkb > i ? (OffT)i : nkb - 1);
                 });
-                pk.template store<0>((uint32_t*)(gx ? xplane(0) : yplane(0)), tt);
+                store(std::integral_constant<int, 0>(), gx ? xplane(0) : yplane(0));
                 fetch(nkb > SLOTS ? SLOTS : nkb - 1);
                 __syncthreads();
                 for (OffT kb = 0; kb < nkb; kb += SLOTS)
                     static_for<SLOTS>([&](auto ic) { body(kb + decltype(ic)::value, ic, reg); });
             };
             if (nkb > 0) {
-                if (gx ? a.kregX : a.kregY) pipeline(std::integral_constant<int, 1>());
+                if (PACKED || (gx ? a.kregX : a.kregY)) pipeline(std::integral_constant<int, 1>());
                 else pipeline(std::integral_constant<int, 0>());
             }
             // centre fragment: the three products added in a fixed order
@@ -1308,6 +1354,50 @@ struct SplitTileOf<OffT, MT, NT, KT, WM, WN, 2, XM, YN> {
     typedef TileSplitWS<OffT, KT, XM, YN> type;
     static constexpr int threads = 512;
 };
+template <typename OffT, int MT, int NT, int KT, int WM, int WN, bool XM, bool YN>
+struct SplitTileOf<OffT, MT, NT, KT, WM, WN, 4, XM, YN> {
+    typedef TileSplitWS<OffT, KT, XM, YN, true> type;
+    static constexpr int threads = 512;
+};
+
+// Split-and-pack pass of the packed split tile: workgroup b packs panel b of
+// X (b < tiles_m * nkb: row panel b / nkb, k block b mod nkb) or of Y (the
+// rest, by column panel).  It gathers the panel's 144 x KT sliver through the
+// offset vectors with the specialised-wave tile's own gather code, splits
+// every element into hi and lo in LDS, and writes the panel out as 16-byte
+// chunks in the order the tile's producer waves copy them.  Rows past m (n)
+// and k past K are packed as zeros, as the tile itself would gather them.
+template <typename OffT, int KT>
+__global__ __launch_bounds__(128) void split_pack_kernel(KArgs<float, OffT> a, void* __restrict__ out) {
+    typedef TileSplitWS<OffT, KT, true, true, true> W;
+    typedef PackQuad<OffT, 144, KT, 128, W::KTP, 1> PQ;
+    typedef typename W::u32x4 u32x4;
+    __shared__ __align__(16) uint32_t planes[PQ::PLANE];  // hi and lo planes, PLANE bf16 each
+    const int tid = threadIdx.x;
+    const OffT nkb = (a.k + KT - 1) / KT;
+    const int64_t b = blockIdx.x, nx = a.tiles_m * (int64_t)nkb;
+    const bool gx = b < nx;
+    const int64_t q = gx ? b : b - nx;
+    const OffT r0 = (OffT)(q / nkb) * 144, kb = (OffT)(q % nkb);
+    PQ pk;
+    if (gx) pk.init(a.rX, r0, a.m, tid, a.xm != 0);
+    else pk.init(a.cY, r0, a.n, tid, a.yn != 0);
+    const float* base = gx ? a.X : a.Y;
+    const int64_t span = gx ? a.spanX : a.spanY;
+    const OffT* gk = gx ? a.cX : a.rY;
+    const OffT sk = uniform((gx ? a.kbsX : a.kbsY)[kb]), kf = uniform(gk[kb * KT]);
+    if (gx ? a.kregX : a.kregY) pk.template load_with<0, 1>(sk, kf, base, span, gk, kb, a.k, tid);
+    else pk.template load_with<0, 0>(sk, kf, base, span, gk, kb, a.k, tid);
+    pk.template store<0>(planes, tid);
+    __syncthreads();
+    const __bf16* lb = (const __bf16*)planes;
+    u32x4* dst = (u32x4*)out + b * W::CH;
+#pragma unroll
+    for (int i = 0; i < W::CPT; ++i) {
+        const int c = 128 * i + tid;
+        dst[c] = *(const u32x4*)(lb + W::chunk_lds(c));
+    }
+}
 
 template <typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT, bool XM, bool YN>
 __global__ __launch_bounds__((SplitTileOf<OffT, MT, NT, KT, WM, WN, LAYOUT, XM, YN>::threads)) void split_kernel(
@@ -1326,12 +1416,34 @@ static int launch_split_tile(const KArgs<float, OffT>& a, bool xm, bool yn, hipS
         return TC_ERR_ARG;
     }
     dim3 grid((unsigned)tiles), block(SplitTileOf<OffT, MT, NT, KT, WM, WN, L, true, true>::threads);
-    if (xm && yn) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, true, true>), grid, block, 0, s, a);
-    else if (xm) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, true, false>), grid, block, 0, s, a);
-    else if (yn) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, false, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, false, false>), grid, block, 0, s, a);
-    hipError_t e = hipGetLastError();
-    return e == hipSuccess ? TC_OK : hip_fail(e, "kernel launch");
+    if constexpr (L == 4) {
+        // the split-and-pack pass, then the tile on the packed panels (the
+        // lane directions matter only to the pass)
+        static_assert(MT == 144 && NT == 144, "the packed split tile is the 144 x 144 pinwheel");
+        if (!a.packed) {
+            set_error("the packed split tile needs its workspace");
+            return TC_ERR_ARG;
+        }
+        const int64_t panels = (a.tiles_m + a.tiles_n) * (int64_t)((a.k + KT - 1) / KT);
+        if (panels > 0x7fffffffLL) {
+            set_error("too many panels for one pack launch");
+            return TC_ERR_ARG;
+        }
+        hipLaunchKernelGGL((split_pack_kernel<OffT, KT>), dim3((unsigned)panels), dim3(128), 0, s, a,
+                           (void*)a.packed);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "kernel launch");
+        hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, true, true>), grid, block, 0, s, a);
+        e = hipGetLastError();
+        return e == hipSuccess ? TC_OK : hip_fail(e, "kernel launch");
+    } else {
+        if (xm && yn) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, true, true>), grid, block, 0, s, a);
+        else if (xm) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, true, false>), grid, block, 0, s, a);
+        else if (yn) hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((split_kernel<OffT, MT, NT, KT, WM, WN, L, false, false>), grid, block, 0, s, a);
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? TC_OK : hip_fail(e, "kernel launch");
+    }
 }
 
 template <typename T, typename OffT, int MT, int NT, int KT, int WM, int WN, int LAYOUT, bool XM, bool YN>
@@ -1712,7 +1824,7 @@ static inline int64_t common_stride(const std::vector<int64_t>& kbs) {
 
 template <typename T, typename OffT>
 static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B,
-                        double beta, void* C, hipStream_t s) {
+                        double beta, void* C, hipStream_t s, void* ws) {
     const OffT* base = (const OffT*)dv.buf;
     KArgs<T, OffT> a;
     a.X = (const T*)(p.swapped ? B : A);
@@ -1741,6 +1853,7 @@ static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, co
     a.ksY = (OffT)common_stride(p.kbsY);
     a.xm = p.x_lanes_m;
     a.yn = p.y_lanes_n;
+    a.packed = ws;
     if (p.m == 0 || p.n == 0) return TC_OK;
     if (p.k_empty || p.k == 0 || alpha == 0.0) {
         int64_t total = p.m * p.n;
@@ -1754,10 +1867,13 @@ static int launch_typed(const Plan& p, const DeviceVectors& dv, double alpha, co
     const bool xm = p.x_lanes_m, yn = p.y_lanes_n;
     if constexpr (sizeof(T) == 4) {
         if (p.mode == TC_SPLIT_BF16X3) {
+            // without a workspace the packed split tile runs as its twin that
+            // splits in its own producer waves (the same bits)
+            const int tile = !ws && split_unpacked_twin(p.tile) >= 0 ? split_unpacked_twin(p.tile) : p.tile;
 #define TC_SCASE(id, MT, NT, KT, WM, WN, L) \
     case id:                                \
         return launch_split_tile<OffT, MT, NT, KT, WM, WN, L>(a, xm, yn, s);
-            switch (p.tile) { TC_TILES_BF16X3(TC_SCASE) }
+            switch (tile) { TC_TILES_BF16X3(TC_SCASE) }
 #undef TC_SCASE
             set_error("unknown tile configuration");
             return TC_ERR_ARG;
@@ -1819,6 +1935,7 @@ __global__ __launch_bounds__((TileOf<T, OffT, MT, NT, KT, WM, WN, L, true, true>
         a.kregY = it.kregY;
         a.ksX = (OffT)it.ksX;
         a.ksY = (OffT)it.ksY;
+        a.packed = nullptr;
         a.xm = it.x_lanes_m;
         a.yn = it.y_lanes_n;
         if (it.x_lanes_m) {

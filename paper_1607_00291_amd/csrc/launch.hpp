@@ -8,9 +8,11 @@
 namespace tc {
 
 // Launch one planned contraction on `stream`.  dv holds the plan's vectors on
-// the current device.  Returns TC_OK or TC_ERR_*.
+// the current device; ws the packed split tile's panels (split_pack_bytes),
+// or null: the packed split tile then runs as its in-kernel-split twin.
+// Returns TC_OK or TC_ERR_*.
 int launch_plan(const Plan& p, const DeviceVectors& dv, double alpha, const void* A, const void* B, double beta,
-                void* C, hipStream_t stream);
+                void* C, hipStream_t stream, void* ws);
 
 // One problem of a batched launch, as seen by the device.  Offset vectors
 // are int32 or int64 for the whole batch.

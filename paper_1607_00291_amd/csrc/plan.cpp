@@ -434,7 +434,7 @@ int choose_tile(const Plan& p, bool batched) {
         // batches run every problem's class from one persistent kernel that
         // holds all four lane variants of the tile; for the pinwheels that
         // kernel spills registers, so by default batches use the other layouts
-        if (batched && (t.layout == 1 || t.layout == 2)) continue;
+        if (batched && (t.layout == 1 || t.layout == 2 || t.layout == 4)) continue;
         // the 32 x 32 tiles win single small launches by parallelism, which a
         // batch supplies from its other problems; inside batches they ran
         // slower than the larger tiles
@@ -451,7 +451,11 @@ int choose_tile(const Plan& p, bool batched) {
         const double store = rounds * w * cus * (double)t.MT * t.NT * esize / (hbm_bw * rate[i].store);
         // where the streaming bound decides, the tile that computes faster
         // wins the tie
-        const double time = std::max(compute, stream) + store + 0.01 * compute;
+        // the packed split tile adds its split-and-pack pass: each operand
+        // element gathered once (4 bytes) and written once as hi and lo
+        // (4 bytes), at about 5 TB/s, plus a second launch
+        const double pack = t.layout == 4 ? (double)split_pack_bytes(t, p.m, p.n, p.k) * 2.0 / 5e12 + 3e-6 : 0.0;
+        const double time = std::max(compute, stream) + store + pack + 0.01 * compute;
         if (time < best_t * 0.999) {
             best_t = time;
             best = i;
@@ -510,7 +514,8 @@ std::string describe_plan(const Plan& p) {
        << ",\"waves\":" << t.waves() << ",\"tiles_m\":" << p.tiles_m << ",\"tiles_n\":" << p.tiles_n
        << ",\"c_tiles_regular\":" << p.c_tiles_regular << ",\"k_blocks\":" << p.kbsX.size()
        << ",\"k_blocks_regular_x\":" << p.k_blocks_regular_x << ",\"k_blocks_regular_y\":" << p.k_blocks_regular_y
-       << ',';
+       << ",\"layout\":" << t.layout << ",\"workspace_bytes\":"
+       << (t.layout == 4 && !p.k_empty ? split_pack_bytes(t, p.m, p.n, p.k) : 0) << ',';
     bool small = (int64_t)std::max({p.rX.size(), p.cY.size(), p.cX.size()}) <= TC_DESCRIBE_MAX_VECTOR;
     if (small) {
         json_vec(os, "rscat_X", p.rX);

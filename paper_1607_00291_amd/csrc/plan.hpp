@@ -3,6 +3,7 @@
 #pragma once
 
 #include <cstdint>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -76,6 +77,9 @@ struct Plan {
 
     mutable std::mutex dev_mu;
     mutable DeviceVectors dev[kMaxDevices];
+    // packed split panels (the packed split tile's workspace), per device:
+    // stream -> (buffer, bytes); guarded by dev_mu
+    mutable std::map<void*, std::pair<void*, size_t>> ws[kMaxDevices];
 
     ~Plan();
 };
@@ -88,8 +92,8 @@ void set_plan_tile(Plan* p, int tile);
 // Pick a tile configuration from the shape (wave-quantisation aware model).
 // Tile configuration of least estimated time; batched skips the pinwheel
 // layouts (a batched launch does not run the all-compute one, and the
-// specialised-wave one spills registers inside the batched kernel) and the
-// 32 x 32 tiles.
+// specialised-wave one spills registers inside the batched kernel), the
+// packed split tile and the 32 x 32 tiles.
 int choose_tile(const Plan& p, bool batched = false);
 // Shape signature used by the autotuner cache.
 std::string plan_signature(const Plan& p);

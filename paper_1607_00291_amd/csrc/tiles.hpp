@@ -13,8 +13,12 @@
 //            waves: four compute waves own one whole rectangle each, four
 //            producer waves gather both operands and do the centre; 3 = the
 //            specialised waves on a regular tile (a 2 x 2 grid of compute
-//            waves, four producer waves)
+//            waves, four producer waves); 4 (split mode) = layout 2 on
+//            operands split once into packed hi/lo panels by a separate pass,
+//            the producer waves only copying them (needs a workspace)
 #pragma once
+
+#include <cstdint>
 
 #define TC_TILES_F64(X)            \
     X(0, 32, 32, 16, 1, 1, 0)      \
@@ -45,7 +49,8 @@
     X(2, 128, 64, 32, 2, 2, 0)     \
     X(3, 128, 128, 32, 2, 2, 0)    \
     X(4, 144, 144, 32, 3, 3, 0)    \
-    X(5, 144, 144, 32, 1, 1, 2)
+    X(5, 144, 144, 32, 1, 1, 2)    \
+    X(6, 144, 144, 32, 1, 1, 4)
 
 namespace tc {
 
@@ -84,8 +89,8 @@ static const TileRate kRatesF64[] = {{31, 31, 2, 1},     {25, 46, 2, 1},       {
 static const TileRate kRatesF32[] = {{50, 57, 2, 1}, {41, 88, 2, 1},       {55, 84, 2, 1},   {68, 94, 2, 1},
                                      {94, 94, 1, 1}, {108.5, 108.5, 1, 0.7}, {83, 85, 2, 0.7}, {90, 90, 1, 0.7},
                                      {54, 60, 2, 1}};
-static const TileRate kRatesBF16x3[] = {{45, 50, 2, 1},   {38, 105, 2, 1},   {59, 104, 2, 1},
-                                        {76, 145, 2, 1},   {144, 144, 1, 1},  {140, 140, 1, 0.7}};
+static const TileRate kRatesBF16x3[] = {{45, 50, 2, 1},   {38, 105, 2, 1},   {59, 104, 2, 1},   {76, 145, 2, 1},
+                                        {144, 144, 1, 1}, {140, 140, 1, 0.7}, {300, 300, 1, 0.7}};
 static_assert(sizeof(kRatesF64) / sizeof(TileRate) == sizeof(kTilesF64) / sizeof(TileCfg), "one rate per tile");
 static_assert(sizeof(kRatesF32) / sizeof(TileRate) == sizeof(kTilesF32) / sizeof(TileCfg), "one rate per tile");
 static_assert(sizeof(kRatesBF16x3) / sizeof(TileRate) == sizeof(kTilesBF16x3) / sizeof(TileCfg), "one rate per tile");
@@ -102,6 +107,28 @@ inline const TileCfg* tile_table(int dtype, int mode) {
     if (dtype == 1 && mode == 0) return kTilesF32;
     if (dtype == 1 && mode == 1) return kTilesBF16x3;
     return nullptr;
+}
+
+// The specialised-wave split tile that gathers and splits in its own
+// producer waves and has the same tile sizes as packed split tile `tile`
+// (their results are the same bits); -1 if there is none.
+inline int split_unpacked_twin(int tile) {
+    const int n = (int)(sizeof(kTilesBF16x3) / sizeof(TileCfg));
+    if (tile < 0 || tile >= n || kTilesBF16x3[tile].layout != 4) return -1;
+    const TileCfg& t = kTilesBF16x3[tile];
+    for (int i = 0; i < n; ++i)
+        if (kTilesBF16x3[i].layout == 2 && kTilesBF16x3[i].MT == t.MT && kTilesBF16x3[i].NT == t.NT &&
+            kTilesBF16x3[i].KT == t.KT)
+            return i;
+    return -1;
+}
+
+// Bytes of the packed split panels of X and Y for m x n x k on packed split
+// tile t: one panel of 2 planes x MT (NT) rows x KT bf16 per row (column)
+// panel and k block.
+inline int64_t split_pack_bytes(const TileCfg& t, int64_t m, int64_t n, int64_t k) {
+    const int64_t nkb = (k + t.KT - 1) / t.KT;
+    return (((m + t.MT - 1) / t.MT) * t.MT + ((n + t.NT - 1) / t.NT) * t.NT) * nkb * t.KT * 4;
 }
 
 inline const TileRate* rate_table(int dtype, int mode) {

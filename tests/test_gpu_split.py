@@ -120,3 +120,147 @@ def test_split_unit_strides_disagree_in_contracted_bundle(oracle_mod, seed):
         print(f"case split p-conflict seed={seed} tile={t}", flush=True)
         got = run(p, "split_bf16x3", tile=t)
         assert np.all(np.abs(got - ref) <= bound + 1e-30), t
+
+
+
+def split_tiles_by_layout(plan):
+    """{layout: tile id} of the split tile table, read through a plan."""
+    from paper_1607_00291_amd import tc
+    keep, out = plan.tile, {}
+    for t in range(tc.tile_count(tc.TC_F32, tc.TC_SPLIT_BF16X3)):
+        plan.tile = t
+        out.setdefault(plan.describe()["layout"], t)
+    plan.tile = keep
+    return out
+
+
+def run_tiles(p, tiles, Ad=None):
+    """Results of one split plan under each tile (fresh C each)."""
+    from paper_1607_00291_amd import tc
+    torch = require_gpu()
+    A = to_dev(p.A, np.float32) if Ad is None else Ad
+    B = to_dev(p.B, np.float32)
+    outs = []
+    for t in tiles:
+        C = to_dev(p.C, np.float32)
+        plan = tc.Plan.for_tensors(A, p.idx_A, B, p.idx_B, C, p.idx_C, mode="split_bf16x3")
+        plan.tile = t
+        plan.execute(A, B, C, p.alpha, p.beta)
+        torch.cuda.synchronize()
+        plan.close()
+        outs.append(to_host(C))
+    return outs
+
+
+def ragged(ext, f, beta, seed):
+    rng = np.random.default_rng(seed)
+    e = {"a": ext, "b": 5, "c": ext + 2, "d": 3, "e": ext + 1, "f": f}
+    mk = lambda lab: f32(inputs.colmajor_from_flat(rng.uniform(-1, 1, int(np.prod(inputs.shape_of(lab, e)))),
+                                                  inputs.shape_of(lab, e)))
+    return inputs.Problem("aebf", "dfce", "abcd", mk("aebf"), mk("dfce"), mk("abcd"), 1.25, beta,
+                          f"ragged{ext}", e)
+
+
+def test_packed_split_tile_same_bits_as_in_kernel_split():
+    """The packed split tile (operands split once into hi/lo panels by a
+    separate pass, the tile's producer waves only copying them) gives the same
+    bits as the specialised-wave tile that gathers and splits in its own
+    producer waves: ragged m, n and k, beta != 0, both gather directions of
+    each operand, the sub-blocked k order and scatter-vector k blocks."""
+    from paper_1607_00291_amd import tc
+    torch = require_gpu()
+    probe = ragged(17, 2, 0.5, 0)
+    A = to_dev(probe.A, np.float32)
+    plan = tc.Plan.for_tensors(A, probe.idx_A, to_dev(probe.B, np.float32), probe.idx_B,
+                               to_dev(probe.C, np.float32), probe.idx_C, mode="split_bf16x3")
+    lay = split_tiles_by_layout(plan)
+    plan.close()
+    packed, twin = lay[4], lay[2]
+    cases = [ragged(ext, f, beta, ext) for ext, f, beta in ((1, 2, 0.5), (17, 1, -1.5), (97, 2, 0.0),
+                                                            (150, 1, 0.5))]
+    cases += [inputs.random_problem(5300 + s, 2, 2, 2, lo=3, hi=40, beta=0.5, alpha=1.25) for s in range(4)]
+    cases.append(inputs.p_conflict_problem(5310, {"e": 13, "g": 3, "f": 10, "i": 150, "j": 70}, beta=-0.5))
+    for p in cases:
+        p = rounded(p)
+        print(f"case packed split {p.name} mnk={p.mnk()}", flush=True)
+        a, b = run_tiles(p, (twin, packed))
+        assert np.array_equal(a, b), p.name
+    torch.cuda.synchronize()
+
+
+def test_packed_split_tile_int64_offsets():
+    """The split-and-pack pass and the packed tile with 64-bit offsets (one
+    operand spanning more than 2^31 bytes): the same bits as the in-kernel
+    split twin, and within the split bound of the oracle."""
+    from paper_1607_00291_amd import tc
+    torch = require_gpu()
+    rng = np.random.default_rng(92)
+    e = {"a": 37, "e": 3, "b": 6, "f": 2, "d": 9, "c": 21}
+    A = f32(inputs.colmajor_from_flat(rng.uniform(-1, 1, 37 * 3 * 6 * 2), (37, 3, 6, 2)))
+    B = f32(inputs.colmajor_from_flat(rng.uniform(-1, 1, 9 * 2 * 21 * 3), (9, 2, 21, 3)))
+    C0 = f32(inputs.colmajor_from_flat(rng.uniform(-1, 1, 37 * 6 * 21 * 9), (37, 6, 21, 9)))
+    p = inputs.Problem("aebf", "dfce", "abcd", A, B, C0, 1.5, -0.5, "int64-offsets", e)
+    big = (1 << 31) // 4
+    storage = torch.zeros(big + 37 * 3 * 6, dtype=torch.float32, device="cuda")
+    Ad = torch.as_strided(storage, (37, 3, 6, 2), (1, 37, 111, big))
+    Ad.copy_(torch.from_numpy(A.astype(np.float32)).to("cuda"))
+    plan = tc.Plan.for_tensors(Ad, p.idx_A, to_dev(B, np.float32), p.idx_B, to_dev(C0, np.float32), p.idx_C,
+                               mode="split_bf16x3")
+    assert plan.describe()["off64"]
+    lay = split_tiles_by_layout(plan)
+    plan.close()
+    print("case packed split int64 offsets", flush=True)
+    a, b = run_tiles(p, (lay[2], lay[4]), Ad=Ad)
+    assert np.array_equal(a, b)
+    del storage, Ad
+    torch.cuda.empty_cache()
+
+
+def test_packed_split_workspace_per_stream_and_graph_replay():
+    """One plan on the packed split tile run on two streams at once with
+    different inputs (each stream has its own panels), then captured on a
+    stream it ran on and replayed with eager work in between: every result
+    equals the in-kernel split twin's, bit for bit."""
+    from paper_1607_00291_amd import tc
+    torch = require_gpu()
+    p1, p2 = rounded(ragged(150, 2, 0.0, 11)), rounded(ragged(150, 2, 0.0, 12))
+    A1, B1, C1 = to_dev(p1.A, np.float32), to_dev(p1.B, np.float32), to_dev(p1.C, np.float32)
+    A2, B2, C2 = to_dev(p2.A, np.float32), to_dev(p2.B, np.float32), to_dev(p2.C, np.float32)
+    plan = tc.Plan.for_tensors(A1, p1.idx_A, B1, p1.idx_B, C1, p1.idx_C, mode="split_bf16x3")
+    lay = split_tiles_by_layout(plan)
+    plan.tile = lay[2]
+    plan.execute(A1, B1, C1, 1.25, 0.0)
+    torch.cuda.synchronize()
+    ref1 = to_host(C1)
+    plan.execute(A2, B2, C2, 1.25, 0.0)
+    torch.cuda.synchronize()
+    ref2 = to_host(C2)
+    plan.tile = lay[4]
+    plan.upload()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    print("case packed split two streams", flush=True)
+    for _ in range(3):
+        C1.zero_()
+        C2.zero_()
+        s1.wait_stream(torch.cuda.current_stream())
+        s2.wait_stream(torch.cuda.current_stream())
+        plan.execute(A1, B1, C1, 1.25, 0.0, stream=s1)
+        plan.execute(A2, B2, C2, 1.25, 0.0, stream=s2)
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(C1), ref1) and np.array_equal(to_host(C2), ref2)
+    print("case packed split graph replay", flush=True)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s1):
+        plan.execute(A1, B1, C1, 1.25, 0.0, stream=s1)
+    for rep in range(3):
+        C1.fill_(float(rep + 7))
+        plan.execute(A2, B2, C2, 1.25, 0.0, stream=s2)  # eager work on another stream's panels
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(C1), ref1), f"replay {rep}"
+        assert np.array_equal(to_host(C2), ref2)
+    del g
+    plan.close()

@@ -301,6 +301,32 @@ def test_tile_table():
             assert MT % 16 == 0 and NT % 16 == 0 and KT % 4 == 0 and waves >= 1
 
 
+def test_packed_split_tile_workspace_and_choice():
+    """The packed split tile needs one panel of 2 planes x 144 rows x 32
+    bf16 per operand row (column) panel and k block; the cost model picks it
+    for the split mode at the v=96/o=24 shape, and no other tile (or mode)
+    reports a workspace."""
+    p = inputs.cfg2()
+    d = describe(p, tc.TC_F32, tc.TC_SPLIT_BF16X3)
+    m, n, k = p.mnk()
+    assert d["layout"] == 4 and (d["MT"], d["NT"], d["KT"]) == (144, 144, 32)
+    panels = (-(-m // 144) + -(-n // 144)) * -(-k // 32)
+    assert d["workspace_bytes"] == panels * 2 * 144 * 32 * 2 == 2 * 2304 * 2304 * 4
+    assert describe(p, tc.TC_F32, tc.TC_NATIVE)["workspace_bytes"] == 0
+    assert describe(p)["workspace_bytes"] == 0
+    # ragged: partial panels are whole panels in the workspace
+    e = {"a": 97, "b": 5, "c": 99, "d": 3, "e": 98, "f": 2}
+    q = inputs.Problem("aebf", "dfce", "abcd", inputs.colmajor(inputs.shape_of("aebf", e)),
+                       inputs.colmajor(inputs.shape_of("dfce", e)), inputs.colmajor(inputs.shape_of("abcd", e)),
+                       1.0, 0.0, "ragged", e)
+    m, n, k = q.mnk()
+    d = describe(q, tc.TC_F32, tc.TC_SPLIT_BF16X3)
+    if d["layout"] == 4:
+        assert d["workspace_bytes"] == (-(-m // 144) + -(-n // 144)) * -(-k // 32) * 18432
+    else:
+        assert d["workspace_bytes"] == 0
+
+
 # --------------------------------------------------------------------------
 # argument validation through the C ABI (no GPU work is started)
 # --------------------------------------------------------------------------

@@ -2,7 +2,9 @@
 on the same inputs: two calls in a row on one GPU, the second with a smaller
 problem (the static offset array keeps the first call's contents), each
 bitwise equal to tc_contract's result (same kernels, same tile, the same
-offset vectors built on the device instead of uploaded)."""
+offset vectors built on the device instead of uploaded; where tc_contract runs
+the packed split tile, which needs a workspace, the allocation-free call runs
+its twin that splits in its own producer waves, with the same bits)."""
 import numpy as np
 import pytest
 
