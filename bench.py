@@ -309,9 +309,12 @@ def _fp32(tc, inputs, steps, warmup, out):
         key = "fp32_v96_o24" if mode == "native" else "split_bf16_v96_o24"
         out[key] = {"gflops": round(fl / ms / 1e6, 1), "ms": round(ms, 4),
                     "frac_of_peak": round(mult * fl / ms / 1e9 / peak, 4),
-                    "peak_tflops": peak, "tile": [d["MT"], d["NT"], d["KT"]]}
+                    "peak_tflops": peak, "tile": [d["MT"], d["NT"], d["KT"]], "layout": d["layout"]}
         if mult == 3:
             out[key]["note"] = "frac counts the three bf16 products (3 * 2mnk) against the dense bf16 peak"
+            if d["workspace_bytes"]:
+                out[key]["workspace_bytes"] = d["workspace_bytes"]
+                out[key]["note"] += "; layout 4: a split-and-pack pass, then the tile on the packed hi/lo panels (both timed)"
         plan.close()
     del A, B, C
     progress("FP32 and split-BF16 at v=96/o=24 done")
