@@ -96,6 +96,8 @@ typedef struct tc_batch tc_batch;
  * call for a descriptor set on a device uploads the plan's offset vectors with
  * a synchronous copy, so a first call must not happen under graph capture
  * (TC_ERR_CAPTURE); use tc_plan_create + tc_plan_upload beforehand instead.
+ * Cached plans live until the process ends, with their device vectors and,
+ * for the packed split tile, their split panels (one set per stream used).
  */
 int tc_contract(double alpha,
                 const void* A, int ndim_A, const int64_t* lens_A, const int64_t* strides_A, const char* idx_A,

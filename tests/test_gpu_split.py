@@ -179,6 +179,8 @@ def test_packed_split_tile_same_bits_as_in_kernel_split():
     cases = [ragged(ext, f, beta, ext) for ext, f, beta in ((1, 2, 0.5), (17, 1, -1.5), (97, 2, 0.0),
                                                             (150, 1, 0.5))]
     cases += [inputs.random_problem(5300 + s, 2, 2, 2, lo=3, hi=40, beta=0.5, alpha=1.25) for s in range(4)]
+    cases += [inputs.random_problem(5320 + s, 1 + s % 3, 1 + (s + 1) % 3, 1 + (s + 2) % 3, lo=2, hi=30, beta=-0.5)
+              for s in range(6)]
     cases.append(inputs.p_conflict_problem(5310, {"e": 13, "g": 3, "f": 10, "i": 150, "j": 70}, beta=-0.5))
     for p in cases:
         p = rounded(p)
