@@ -47,7 +47,9 @@
  *     allocated), freed by tc_plan_destroy.  Calls on one stream are ordered
  *     by the stream; calls on different streams use different workspaces.
  *     A graph captured on a stream uses that stream's workspace, so its
- *     replays must not overlap eager calls of the plan on that stream.
+ *     replays must not overlap eager calls of the plan on that stream.  The
+ *     tile choice leaves the packed split tile out when its workspace would
+ *     exceed 8 GiB (tc_plan_set_tile may still select it).
  *   - stream is a hipStream_t (NULL = the null stream).  Calls are
  *     asynchronous on it; device faults surface at the caller's next
  *     synchronisation.  The results of one plan and one tile configuration

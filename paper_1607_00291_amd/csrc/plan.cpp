@@ -435,6 +435,7 @@ int choose_tile(const Plan& p, bool batched) {
         // holds all four lane variants of the tile; for the pinwheels that
         // kernel spills registers, so by default batches use the other layouts
         if (batched && (t.layout == 1 || t.layout == 2 || t.layout == 4)) continue;
+        if (t.layout == 4 && split_pack_bytes(t, p.m, p.n, p.k) > kMaxSplitPanelBytes) continue;
         // the 32 x 32 tiles win single small launches by parallelism, which a
         // batch supplies from its other problems; inside batches they ran
         // slower than the larger tiles

@@ -130,6 +130,9 @@ inline int64_t split_pack_bytes(const TileCfg& t, int64_t m, int64_t n, int64_t 
     const int64_t nkb = (k + t.KT - 1) / t.KT;
     return (((m + t.MT - 1) / t.MT) * t.MT + ((n + t.NT - 1) / t.NT) * t.NT) * nkb * t.KT * 4;
 }
+// The cost model leaves the packed split tile out above this many bytes of
+// panels (the in-kernel split needs no workspace).
+static constexpr int64_t kMaxSplitPanelBytes = int64_t(8) << 30;
 
 inline const TileRate* rate_table(int dtype, int mode) {
     if (dtype == 0 && mode == 0) return kRatesF64;

@@ -325,6 +325,11 @@ def test_packed_split_tile_workspace_and_choice():
         assert d["workspace_bytes"] == (-(-m // 144) + -(-n // 144)) * -(-k // 32) * 18432
     else:
         assert d["workspace_bytes"] == 0
+    # above 8 GiB of panels the model leaves the packed tile out (m = n = 2^18,
+    # k = 2^13: about 17 GB of panels); descriptors only, nothing is allocated
+    big = tc.describe((1 << 18, 1 << 13), (1, 1 << 18), "ik", (1 << 13, 1 << 18), (1, 1 << 13), "kj",
+                      (1 << 18, 1 << 18), (1, 1 << 18), "ij", tc.TC_F32, tc.TC_SPLIT_BF16X3)
+    assert big["layout"] != 4 and big["workspace_bytes"] == 0
 
 
 # --------------------------------------------------------------------------
