@@ -89,6 +89,9 @@ static const TileRate kRatesF64[] = {{31, 31, 2, 1},     {25, 46, 2, 1},       {
 static const TileRate kRatesF32[] = {{50, 57, 2, 1}, {41, 88, 2, 1},       {55, 84, 2, 1},   {68, 94, 2, 1},
                                      {94, 94, 1, 1}, {108.5, 108.5, 1, 0.7}, {83, 85, 2, 0.7}, {90, 90, 1, 0.7},
                                      {54, 60, 2, 1}};
+// Split-BF16 rates count FP32-equivalent flops (one update = three bf16
+// products).  The packed split tile's rate is that of its tile alone on the
+// v=96/o=24 shape (2304^3); choose_tile adds its split-and-pack pass.
 static const TileRate kRatesBF16x3[] = {{45, 50, 2, 1},   {38, 105, 2, 1},   {59, 104, 2, 1},   {76, 145, 2, 1},
                                         {144, 144, 1, 1}, {140, 140, 1, 0.7}, {300, 300, 1, 0.7}};
 static_assert(sizeof(kRatesF64) / sizeof(TileRate) == sizeof(kTilesF64) / sizeof(TileCfg), "one rate per tile");
