@@ -1148,9 +1148,10 @@ struct PackQuad {
 // (the 3 x 3 wave grid puts three waves on one SIMD).
 //
 // PACKED: the operands were split once beforehand (split_pack_kernel) into
-// panels laid out as the LDS stages hold them, so the producer waves only
-// copy each stage's two panels with 16-byte loads; the compute side is the
-// same, and so are the results, bit for bit.
+// panels of 16-byte chunks (unpadded rows of hi, then of lo), so the producer
+// waves only copy each stage's two panels with 16-byte loads into the padded
+// LDS rows; the compute side is the same, and so are the results, bit for
+// bit.
 template <typename OffT, int KT, bool XM, bool YN, bool PACKED = false>
 struct TileSplitWS {
     static constexpr int MT = 144, NT = 144, NTHR = 512;
