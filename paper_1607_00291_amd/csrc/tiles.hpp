@@ -90,10 +90,13 @@ static const TileRate kRatesF32[] = {{50, 57, 2, 1}, {41, 88, 2, 1},       {55, 
                                      {94, 94, 1, 1}, {108.5, 108.5, 1, 0.7}, {83, 85, 2, 0.7}, {90, 90, 1, 0.7},
                                      {54, 60, 2, 1}};
 // Split-BF16 rates count FP32-equivalent flops (one update = three bf16
-// products).  The packed split tile's rate is that of its tile alone on the
-// v=96/o=24 shape (2304^3); choose_tile adds its split-and-pack pass.
-static const TileRate kRatesBF16x3[] = {{45, 50, 2, 1},   {38, 105, 2, 1},   {59, 104, 2, 1},   {76, 145, 2, 1},
-                                        {144, 144, 1, 1}, {140, 140, 1, 0.7}, {300, 300, 1, 0.7}};
+// products).  The packed split tile's rate is its tile alone on 2304^3
+// (72.2 us per 24.46 GFLOP); choose_tile adds its split-and-pack pass.  With
+// the 32 x 32 and 64 x 64 rates the model picks the fastest measured split
+// tile on 1024^3 to 2048^3, 4096^2 x 1024 and 1024^2 x 8192 (512^3: a tile
+// within 15% of the fastest).
+static const TileRate kRatesBF16x3[] = {{45, 40, 2, 1},   {57, 105, 2, 1},   {59, 104, 2, 1},   {76, 145, 2, 1},
+                                        {144, 144, 1, 1}, {140, 140, 1, 0.7}, {340, 340, 1, 0.7}};
 static_assert(sizeof(kRatesF64) / sizeof(TileRate) == sizeof(kTilesF64) / sizeof(TileCfg), "one rate per tile");
 static_assert(sizeof(kRatesF32) / sizeof(TileRate) == sizeof(kTilesF32) / sizeof(TileCfg), "one rate per tile");
 static_assert(sizeof(kRatesBF16x3) / sizeof(TileRate) == sizeof(kTilesBF16x3) / sizeof(TileCfg), "one rate per tile");
