@@ -202,7 +202,8 @@ int tc_plan_destroy(tc_plan* plan);
 /*
  * JSON description of a plan, for inspection and tests (host only): bundles
  * in planned order with lengths and strides, whether A and B were swapped,
- * m, n, k, tile configuration, the lane-fast dimension of each operand,
+ * m, n, k, tile configuration (with its "layout" and the device workspace it
+ * needs, "workspace_bytes"), the lane-fast dimension of each operand,
  * counts of constant-stride blocks, and (for problems with at most
  * `TC_DESCRIBE_MAX_VECTOR` entries per vector) the scatter and block-stride
  * vectors.  Writes at most len bytes including the NUL; returns the full
